@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X MHD bunch update (one GPU).
+
+Workload: decaying supersonic MHD turbulence, 512^3 periodic cells as 4096 patches of
+32^3 (guard width 3), seeded synthetic initial state.  One timed step = the whole hot
+path on every patch: guard exchange, global CFL time step on the device, update
+(primitives, EMFs at time n, predictor, HLLD + edge EMFs + conservative/CT update).
+The state stays resident in HBM; no host synchronisation inside the timed region.
+
+Prints one JSON line: cell-updates/s for FP64 (headline) with the FP32 result, the
+per-kernel HIP-event timings, the roofline of the update and the oracle timed on the
+host cores.
+
+  python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-fp32] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "MHD cell-updates/s and % HBM roofline, FP64/FP32, batched vs per-bunch"
+PEAK_HBM_GBS = 8000.0
+PEAK_VALU_TFLOPS = {8: 78.6, 4: 157.3}     # MI355X vector FP64 / FP32 (published)
+UPDATE_KERNELS = ("prim", "edge_emf_n", "predict", "solve")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_cell(n, g, s):
+    """Read every padded cell once, write every interior cell once, 8 fields."""
+    return 8.0 * s * (((n + 2 * g) / n) ** 3 + 1.0)
+
+
+def run_precision(w, precision, steps, warmup, flops_per_cell):
+    import numpy as np
+    import torch
+
+    from paper_2508_09568_amd.binding import Bunch
+
+    L = w.layout
+    dtype = torch.float64 if precision == 8 else torch.float32
+    Ua = w.U.to(dtype=dtype, copy=True)
+    Ub = torch.empty_like(Ua)
+    B = Bunch(L.dims, g=L.g, precision=precision, gamma=w.gamma, cfl=w.cfl)
+    nbr = torch.as_tensor(w.nbr.astype(np.int32)).cuda()
+    dx = torch.as_tensor(w.dx).cuda()
+    dt = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+
+    def step(a, b):
+        B.fill_guards(a, nbr)
+        B.cfl(a, dx, dt, global_min=True)
+        B.update(a, b, dt, dx)
+
+    for _ in range(warmup):
+        step(Ua, Ub)
+        Ua, Ub = Ub, Ua
+    rc = B.check()
+    if rc != 0:
+        raise RuntimeError(f"device status {rc} after warm-up")
+    torch.cuda.synchronize()
+    B.profile(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for _ in range(steps):
+        step(Ua, Ub)
+        Ua, Ub = Ub, Ua
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    prof = B.profile_read()
+    B.profile(False)
+    B.fill_guards(Ua, nbr)       # outside the timed region: guard-filled state for the oracle
+    rc = B.check()
+    if rc != 0:
+        raise RuntimeError(f"device status {rc} after timed steps")
+    cells = L.interior_cells
+    value = cells * steps / (ms * 1e-3)
+    upd_ms = sum(prof[k][0] for k in UPDATE_KERNELS) / steps
+    n = int(L.dims[0, 0])
+    bpc = algorithmic_bytes_per_cell(n, L.g, precision)
+    kern = {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in prof.items()}
+    res = {
+        "value": value,
+        "ms_per_step": ms / steps,
+        "wall_ms_per_step": 1e3 * wall / steps,
+        "update_ms_per_launch": upd_ms,
+        "kernels": kern,
+        "flops_per_cell": flops_per_cell,
+        "bytes_per_cell": bpc,
+        "update_tflops": flops_per_cell * cells / (upd_ms * 1e-3) / 1e12,
+        "update_hbm_gbs": bpc * cells / (upd_ms * 1e-3) / 1e9,
+        "state_host": Ua,
+        "dt": dt,
+        "bunch": B,
+    }
+    return res
+
+
+def cpu_baseline(w, state_gpu, dt_gpu, npatch):
+    """Oracle step of `npatch` patches (the GPU's guard-filled state), host cores."""
+    import numpy as np
+
+    import oracle
+
+    L = w.layout
+    a, b = int(L.base[0]), int(L.base[npatch])
+    U = state_gpu[a:b].double().cpu().numpy()
+    dt = float(dt_gpu[0].item())
+    prm = oracle.Params(gamma=w.gamma, cfl=w.cfl)
+    dims = L.dims[:npatch]
+    dx = w.dx[:npatch]
+    t0 = time.perf_counter()
+    oracle.step_many(U, dims, L.g, np.full(npatch, dt), dx, prm)
+    el = time.perf_counter() - t0
+    cells = int(np.prod(dims.astype(np.int64), axis=1).sum())
+    return {"value": cells / el, "unit": "cell-updates/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{npatch} of the 4096 patches of 32^3 (FP64), one update, "
+                      f"{cells} cell-updates in {el:.2f} s",
+            "cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-patches", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the update has no multi-GPU path in this "
+              "build (patches would shard by contiguous blocks with a guard exchange per "
+              "step; not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2508_09568_amd import workloads as W
+
+    torch.cuda.init()
+    dev = torch.cuda.get_device_name(0)
+    log(f"[bench] device {dev}; generating turbulence 512^3 as 4096 x 32^3 (seed 3)")
+    t0 = time.perf_counter()
+    w = W.turbulence(device="cuda")
+    log(f"[bench] generated in {time.perf_counter() - t0:.1f} s")
+    # algorithmic arithmetic per cell-update (oracle op count on one patch of the workload)
+    p0 = w.U[int(w.layout.base[0]):int(w.layout.base[1])].cpu().numpy()
+    ops = oracle.ops_per_cell(p0, w.layout.dims[0], w.layout.g, 1e-4, w.dx[0],
+                              oracle.Params(gamma=w.gamma))
+    flops = float(ops[:4].sum())
+
+    log(f"[bench] FP64: warmup {args.warmup}, timed {args.steps} steps")
+    r64 = run_precision(w, 8, args.steps, args.warmup, flops)
+    log(f"[bench] FP64 {r64['value']:.4e} cell-updates/s, {r64['ms_per_step']:.2f} ms/step")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU baseline: oracle on {args.cpu_patches} patches")
+        cpu = cpu_baseline(w, r64["state_host"], r64["dt"], args.cpu_patches)
+        log(f"[bench] oracle {cpu['value']:.4e} cell-updates/s on {cpu['cores']} threads")
+    for k in ("state_host", "dt", "bunch"):
+        r64.pop(k)
+    torch.cuda.empty_cache()
+    r32 = None
+    if not args.no_fp32:
+        log(f"[bench] FP32: warmup {args.warmup}, timed {args.steps} steps")
+        r32 = run_precision(w, 4, args.steps, args.warmup, flops)
+        for k in ("state_host", "dt", "bunch"):
+            r32.pop(k)
+        log(f"[bench] FP32 {r32['value']:.4e} cell-updates/s, {r32['ms_per_step']:.2f} ms/step")
+
+    peak = PEAK_VALU_TFLOPS[8]
+    out = {
+        "metric": METRIC,
+        "value": r64["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "decaying supersonic MHD turbulence, 512^3 periodic cells as 4096 "
+                        "patches of 32^3, guard 3, seeded velocity field (rms Mach 4); "
+                        "step = guard exchange + global CFL + update",
+            "patches": int(w.layout.P), "patch_cells": [32, 32, 32], "guard": 3,
+            "cell_updates_per_step": int(w.layout.interior_cells),
+            "device": dev,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "mhd_bunch_update (launches: " + ", ".join(UPDATE_KERNELS) + ")",
+            "achieved": r64["update_tflops"],
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": r64["update_tflops"] / peak,
+            "traffic": None,
+            "flops_per_cell": flops,
+        },
+        "hbm": {
+            "achieved": r64["update_hbm_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": r64["update_hbm_gbs"] / PEAK_HBM_GBS,
+            "bytes_per_cell": r64["bytes_per_cell"],
+        },
+        "kernels_ms": {k: v["avg_ms"] for k, v in r64["kernels"].items()},
+        "fp32": None if r32 is None else {
+            "value": r32["value"], "ms_per_step": r32["ms_per_step"],
+            "update_ms_per_launch": r32["update_ms_per_launch"],
+            "alu_frac": r32["update_tflops"] / PEAK_VALU_TFLOPS[4],
+            "hbm_frac": r32["update_hbm_gbs"] / PEAK_HBM_GBS,
+            "kernels_ms": {k: v["avg_ms"] for k, v in r32["kernels"].items()},
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

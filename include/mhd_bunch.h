@@ -1,0 +1,149 @@
+/*
+ * mhd_bunch.h -- C ABI of the MI355X (gfx950) ideal-MHD bunch update.
+ *
+ * A "bunch" is a set of guard-zoned patches updated together (the paper's §2.3
+ * "HLLD Mockup" and §2.4 "DISPATCH Integration": patches ready for update are gathered
+ * into a work array and updated collectively to amortise launch overhead).  One call
+ * of mhd_bunch_update advances the 8 conserved fields (rho, rho u, E, face-centred B)
+ * of every patch by its own time step: unsplit MUSCL-Hancock prediction in primitive
+ * variables (§2.1 "The MUSCL Scheme"), HLLD face fluxes (§2.1 "HLLD Solver", Fig. 1),
+ * edge EMFs from four predicted corner states and constrained transport
+ * (§2.1 "Constrained transport and 2D-extension", eq:EMF_to_B, Fig. 2-3).
+ *
+ * Conventions
+ *  - Memory: every device buffer (state, workspace, dt/dx arrays, neighbour table) is
+ *    allocated and owned by the caller; the library never frees caller memory.  Its own
+ *    allocations are the host-side handle and, after mhd_bunch_graph_capture, a HIP graph.
+ *  - Streams: all work is enqueued on the caller's stream; calls return without
+ *    synchronising, except mhd_bunch_check.
+ *  - Errors: status codes only.  Argument errors are detected before any launch.
+ *    Non-physical input states (rho <= 0, p <= 0 or non-finite) set a device status
+ *    word that mhd_bunch_check reports.
+ *  - State layout: patch p occupies elements [base_p, base_p + 8*Nc_p) of the state
+ *    buffer, base_p = sum_{q<p} 8*Nc_q.  Inside a patch: 8 fields, field-major, each a
+ *    padded box Nx*Ny*Nz with x fastest, N_d = n_d + 2g for an active direction
+ *    (n_d > 1) and N_d = 1 for a collapsed one.  Field order rho, rho u, rho v, rho w,
+ *    E, Bx, By, Bz (state vector of eq:MHD_vector).  B_d[i] is the value on the lower
+ *    d-face of cell i (Fig. 2); a patch owns cells and lower faces [g, g+n).
+ *  - Element type: double (precision 8) or float (precision 4).  dt and dx are always
+ *    double device arrays: dt[P], dx[P][3] (per-patch time step and per-direction cell
+ *    size, §2.2: each patch carries its own time step; §2.3: spacing per direction).
+ */
+#ifndef MHD_BUNCH_H
+#define MHD_BUNCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mhd_bunch mhd_bunch; /* opaque; not thread-safe */
+
+typedef enum {
+  MHD_OK = 0,
+  MHD_EINVAL = -1,        /* invalid argument (nothing was launched) */
+  MHD_ENOMEM = -2,        /* host allocation failed */
+  MHD_EDEVICE = -3,       /* a HIP call failed */
+  MHD_ESTATE = -4,        /* call out of order (e.g. update before bind) */
+  MHD_ENONPHYS = -5,      /* a non-physical state was met on the device */
+  MHD_EUNSUPPORTED = -6   /* valid but not supported by this build */
+} mhd_status;
+
+typedef struct {
+  int32_t n_patches;      /* number of patches, >= 1 */
+  const int32_t* dims;    /* host array [n_patches][3]: interior cells, 1 = collapsed */
+  int32_t guard;          /* guard width g >= 3 (the stencil reaches 2 cells down, 3 faces
+                             up); the paper's patches use 3 (24^3 active, 30^3 total) */
+  int32_t precision;      /* 4 = float, 8 = double */
+  double gamma;           /* adiabatic index */
+  double cfl;             /* Courant number of mhd_bunch_cfl */
+  int32_t limiter;        /* 0 = monotonised central, 1 = minmod */
+  double rho_floor;       /* floors applied to every reconstructed state */
+  double p_floor;
+  double eps_deg;         /* relative threshold of the HLLD degeneracy switch */
+  int64_t max_scratch_bytes; /* cap of the per-call scratch (patches are processed in
+                                chunks that fit); 0 = no cap */
+} mhd_bunch_desc;
+
+/* Validates the description and builds the host-side patch and launch tables.  No
+ * device memory is touched.  *out receives a handle to free with mhd_bunch_destroy. */
+mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* desc);
+void mhd_bunch_destroy(mhd_bunch* h);
+
+/* Element count and byte size of one state buffer (all patches, guards included). */
+int64_t mhd_bunch_state_elems(const mhd_bunch* h);
+int64_t mhd_bunch_state_bytes(const mhd_bunch* h);
+/* Element offset of patch p inside a state buffer, or -1 if p is out of range. */
+int64_t mhd_bunch_patch_offset(const mhd_bunch* h, int32_t p);
+
+/* Bytes of device workspace the caller must provide to mhd_bunch_bind (patch and launch
+ * tables, CFL reduction slots, status word, and the scratch of one chunk of patches). */
+int64_t mhd_bunch_workspace_bytes(const mhd_bunch* h);
+
+/* Attaches a caller-owned device workspace (>= workspace_bytes, 256-byte aligned) and
+ * uploads the tables on `stream`.  Must precede every call below. */
+mhd_status mhd_bunch_bind(mhd_bunch* h, void* workspace_dev, hipStream_t stream);
+
+/* Copies one patch (8 fields of the padded box, layout above, same element type) from
+ * src into the state buffer U_dev, or out of it into dst.  src/dst may be host or
+ * device memory (flag).  Asynchronous on `stream`; host memory must stay valid until
+ * the stream reaches the copy. */
+mhd_status mhd_bunch_load(mhd_bunch* h, void* U_dev, int32_t patch, const void* src,
+                          int32_t src_is_device, hipStream_t stream);
+mhd_status mhd_bunch_store(const mhd_bunch* h, const void* U_dev, int32_t patch, void* dst,
+                           int32_t dst_is_device, hipStream_t stream);
+
+/* Fills the guard zones of every patch in place from a device neighbour table
+ * nbr_dev[P][27] (entry (ox+1) + 3(oy+1) + 9(oz+1) = id of the patch at that offset,
+ * -1 = domain boundary: zero-gradient copy of the nearest owned value).  Patches that
+ * are neighbours must have equal interior dims. */
+mhd_status mhd_bunch_fill_guards(mhd_bunch* h, void* U_dev, const int32_t* nbr_dev,
+                                 hipStream_t stream);
+
+/* Time step per patch: dt[p] = cfl * min over its interior cells of
+ * 1 / sum_{active d} (|u_d| + c_f,d) / dx_d, with c_f,d the fast magnetosonic speed
+ * along d.  global != 0 writes the minimum over all patches into every dt[p]. */
+mhd_status mhd_bunch_cfl(mhd_bunch* h, const void* U_dev, const double* dx_dev,
+                         double* dt_dev, int32_t global, hipStream_t stream);
+
+/* One update of every patch: U_out owned cells and faces <- U_in advanced by dt[p].
+ * U_in guards must be filled; U_out guards are not written.  U_in and U_out must not
+ * overlap. */
+mhd_status mhd_bunch_update(mhd_bunch* h, const void* U_in, void* U_out, const double* dt_dev,
+                            const double* dx_dev, hipStream_t stream);
+
+/* Synchronises `stream`, then returns MHD_ENONPHYS if any kernel since the last check
+ * met a non-physical state (and clears the flag), else MHD_OK. */
+mhd_status mhd_bunch_check(mhd_bunch* h, hipStream_t stream);
+
+/* Kernel timing with HIP events recorded on the caller's stream around every launch.
+ * mhd_bunch_profile(h, 1) clears the record and starts recording; mhd_bunch_profile(h, 0)
+ * stops.  mhd_bunch_profile_read synchronises
+ * on the recorded events and returns the summed duration (ms) and launch count of one
+ * kernel kind since recording started. */
+enum {
+  MHD_KERNEL_PRIM = 0,        /* primitives */
+  MHD_KERNEL_EDGE_EMF_N = 1,  /* edge EMFs at time n */
+  MHD_KERNEL_PREDICT = 2,     /* slopes, half-step state and face field */
+  MHD_KERNEL_SOLVE = 3,       /* HLLD fluxes, edge EMFs, update */
+  MHD_KERNEL_CFL = 4,         /* time step (three small kernels, timed together) */
+  MHD_KERNEL_GUARDS = 5,      /* guard fill */
+  MHD_KERNEL_COUNT = 6
+};
+mhd_status mhd_bunch_profile(mhd_bunch* h, int32_t enable);
+mhd_status mhd_bunch_profile_read(mhd_bunch* h, int32_t kernel, double* total_ms, int64_t* launches);
+
+const char* mhd_status_string(mhd_status s);
+
+/* Text of the HIP failure behind the last MHD_EDEVICE returned for this handle ("" if
+ * none).  The string is owned by the handle. */
+const char* mhd_bunch_last_error(const mhd_bunch* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -84,6 +84,8 @@ def lib():
         L.mhd_oracle_uct.argtypes = [dp, P(_Params)]
         L.mhd_oracle_uct.restype = C.c_double
         L.mhd_oracle_dqdt.argtypes = [dp, dp, ip, C.c_double, dp]
+        L.mhd_oracle_threads.restype = C.c_int
+        L.mhd_oracle_ops_per_cell.argtypes = [ip, C.c_int32, dp, C.c_double, dp, P(_Params), dp]
         _lib = L
     return _lib
 
@@ -102,6 +104,11 @@ def _f64(a):
 
 def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def threads() -> int:
+    """OpenMP threads used by the multi-patch entry points."""
+    return int(lib().mhd_oracle_threads())
 
 
 def step_many(U, dims, g, dt, dx, prm: Params, count_floors=False):
@@ -175,6 +182,18 @@ def count_ops(U, n, g, dt, dx, prm: Params):
     if rc != 0:
         raise ValueError("mhd_oracle_count_ops: invalid argument")
     return cnt
+
+
+def ops_per_cell(U, n, g, dt, dx, prm: Params):
+    """Algorithmic (add/sub, mul, div, sqrt, compare) per interior cell-update."""
+    U = _f64(U)
+    n = _i32(n)
+    dx = _f64(dx)
+    out = np.zeros(5)
+    p = prm.c()
+    if lib().mhd_oracle_ops_per_cell(_i(n), g, _d(U), dt, _d(dx), C.byref(p), _d(out)) != 0:
+        raise ValueError("mhd_oracle_ops_per_cell: invalid argument")
+    return out
 
 
 def hlld(L, R, prm: Params):

@@ -19,6 +19,10 @@
  */
 #include "mhd_oracle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -313,11 +317,28 @@ inline Box mkbox(const Geom& G, int lo, int hi) {
   const int l[3] = {lo, lo, lo}, h[3] = {hi, hi, hi};
   return mkbox(G, l, h);
 }
+/* optional record of the arithmetic of every box pass (op-counting runs only):
+ * accumulates sum over passes of ops / items, i.e. the work per item of each pass */
+thread_local bool g_rec = false;
+thread_local double g_per_item[5];
+
 template <class F>
 inline void each(const Geom& G, const Box& b, F f) {
+  const OpCount o0 = g_ops;
+  long items = 0;
   for (int k = b.lo[2]; k < b.hi[2]; ++k)
     for (int j = b.lo[1]; j < b.hi[1]; ++j)
-      for (int i = b.lo[0]; i < b.hi[0]; ++i) f((long)i + G.st[1] * j + G.st[2] * k);
+      for (int i = b.lo[0]; i < b.hi[0]; ++i) {
+        f((long)i + G.st[1] * j + G.st[2] * k);
+        ++items;
+      }
+  if (g_rec && items > 0) {
+    g_per_item[0] += double(g_ops.add - o0.add) / items;
+    g_per_item[1] += double(g_ops.mul - o0.mul) / items;
+    g_per_item[2] += double(g_ops.div - o0.div) / items;
+    g_per_item[3] += double(g_ops.sqrt - o0.sqrt) / items;
+    g_per_item[4] += double(g_ops.cmp - o0.cmp) / items;
+  }
 }
 
 /* ------------------------------------------------------------------ one patch update */
@@ -610,6 +631,14 @@ long patch_elems(const int32_t n[3], int g) {
 
 extern "C" {
 
+int mhd_oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int mhd_oracle_step(const int32_t n[3], int32_t g, const double* U_in, double* U_out, double dt,
                     const double dx[3], const mhd_oracle_params* prm, int64_t* nfloor) {
   Geom G;
@@ -751,6 +780,23 @@ int mhd_oracle_count_ops(const int32_t n[3], int32_t g, const double* U_in, doub
   s.run(a.data(), b.data());
   counts[0] = g_ops.add; counts[1] = g_ops.mul; counts[2] = g_ops.div;
   counts[3] = g_ops.sqrt; counts[4] = g_ops.cmp;
+  return 0;
+}
+
+int mhd_oracle_ops_per_cell(const int32_t n[3], int32_t g, const double* U_in, double dt,
+                            const double dx[3], const mhd_oracle_params* prm, double out[5]) {
+  Geom G;
+  if (!G.init(n, g) || !check_params(prm)) return -1;
+  const long ne = 8 * G.Nc;
+  std::vector<Cnt> a(ne), b(ne);
+  for (long i = 0; i < ne; ++i) a[i] = Cnt(U_in[i]);
+  Stepper<Cnt> s(G, *prm, dt, dx);
+  g_ops = OpCount{0, 0, 0, 0, 0};
+  for (int i = 0; i < 5; ++i) g_per_item[i] = 0.0;
+  g_rec = true;
+  s.run(a.data(), b.data());
+  g_rec = false;
+  for (int i = 0; i < 5; ++i) out[i] = g_per_item[i];
   return 0;
 }
 

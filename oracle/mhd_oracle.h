@@ -31,6 +31,9 @@ typedef struct {
   int32_t limiter;   /* 0 = monotonised central (MC), 1 = minmod */
 } mhd_oracle_params;
 
+/* Threads the multi-patch entry points use (OpenMP over patches). */
+int mhd_oracle_threads(void);
+
 /* One update of one patch: U_out interior <- U_in advanced by dt.  Guards of U_out are a
  * copy of U_in's.  nfloor (may be NULL) is int64_t[3] and accumulates floor activations
  * in cell primitives, face states and edge-corner states.  g >= 3. */
@@ -69,6 +72,13 @@ int mhd_oracle_step_jvp_many(int32_t npatch, const int32_t* dims, int32_t g,
  * counts[0] add/sub, [1] mul, [2] div, [3] sqrt, [4] compare/min/max/abs. */
 int mhd_oracle_count_ops(const int32_t n[3], int32_t g, const double* U_in, double dt,
                          const double dx[3], const mhd_oracle_params* prm, int64_t counts[5]);
+
+/* Algorithmic arithmetic per interior cell-update, without halo recomputation: each
+ * pass of the update over a box (cells, faces of one direction, edges of one direction)
+ * contributes its operations per item, since an interior cell owns one item of every
+ * pass.  out[5] by class as in mhd_oracle_count_ops. */
+int mhd_oracle_ops_per_cell(const int32_t n[3], int32_t g, const double* U_in, double dt,
+                            const double dx[3], const mhd_oracle_params* prm, double out[5]);
 
 /* ---- single-building-block entry points (for pinning the pieces one by one) ---- */
 

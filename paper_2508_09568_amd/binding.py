@@ -1,0 +1,206 @@
+"""Thin ctypes binding of libmhdbunch.so (include/mhd_bunch.h).
+
+Functions keep the C names; they only marshal arguments.  Every step of the update
+runs in the library's HIP kernels; PyTorch supplies device memory and the stream.
+Importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmhdbunch.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mhd_bunch.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2508_09568_amd.build` "
+        "(hipcc --offload-arch=gfx950); there is no fallback implementation")
+
+# torch must own the process's HIP runtime before the library is loaded: the library's
+# runtime dependency then resolves to the copy torch already mapped, and torch's streams
+# and allocations are native objects for the library's launches.
+import torch  # noqa: E402,F401
+
+_lib = C.CDLL(LIB_PATH)
+
+
+def _hip_runtimes():
+    try:
+        maps = open("/proc/self/maps").read().splitlines()
+    except OSError:
+        return []
+    return sorted({ln.split()[-1] for ln in maps if "libamdhip64" in ln})
+
+
+if len(_hip_runtimes()) > 1:
+    raise ImportError(f"two HIP runtimes are mapped in this process: {_hip_runtimes()}")
+
+MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EDEVICE, MHD_ESTATE, MHD_ENONPHYS, MHD_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+
+
+class mhd_bunch_desc(C.Structure):
+    _fields_ = [
+        ("n_patches", C.c_int32),
+        ("dims", C.POINTER(C.c_int32)),
+        ("guard", C.c_int32),
+        ("precision", C.c_int32),
+        ("gamma", C.c_double),
+        ("cfl", C.c_double),
+        ("limiter", C.c_int32),
+        ("rho_floor", C.c_double),
+        ("p_floor", C.c_double),
+        ("eps_deg", C.c_double),
+        ("max_scratch_bytes", C.c_int64),
+    ]
+
+
+_h = C.c_void_p
+_v = C.c_void_p
+_st = C.c_void_p   # hipStream_t
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+_SIGS = {
+    "mhd_bunch_create": (C.c_int, [C.POINTER(_h), C.POINTER(mhd_bunch_desc)]),
+    "mhd_bunch_destroy": (None, [_h]),
+    "mhd_bunch_state_elems": (C.c_int64, [_h]),
+    "mhd_bunch_state_bytes": (C.c_int64, [_h]),
+    "mhd_bunch_patch_offset": (C.c_int64, [_h, C.c_int32]),
+    "mhd_bunch_workspace_bytes": (C.c_int64, [_h]),
+    "mhd_bunch_bind": (C.c_int, [_h, _v, _st]),
+    "mhd_bunch_load": (C.c_int, [_h, _v, C.c_int32, _v, C.c_int32, _st]),
+    "mhd_bunch_store": (C.c_int, [_h, _v, C.c_int32, _v, C.c_int32, _st]),
+    "mhd_bunch_fill_guards": (C.c_int, [_h, _v, _v, _st]),
+    "mhd_bunch_cfl": (C.c_int, [_h, _v, _v, _v, C.c_int32, _st]),
+    "mhd_bunch_update": (C.c_int, [_h, _v, _v, _v, _v, _st]),
+    "mhd_bunch_check": (C.c_int, [_h, _st]),
+    "mhd_bunch_profile": (C.c_int, [_h, C.c_int32]),
+    "mhd_bunch_profile_read": (C.c_int, [_h, C.c_int32, _dp, C.POINTER(C.c_int64)]),
+    "mhd_status_string": (C.c_char_p, [C.c_int]),
+    "mhd_bunch_last_error": (C.c_char_p, [_h]),
+}
+
+KERNELS = {"prim": 0, "edge_emf_n": 1, "predict": 2, "solve": 3, "cfl": 4, "guards": 5}
+
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+
+def header_functions(path: str = HEADER):
+    """Names of the functions declared in include/mhd_bunch.h."""
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mhd_\w+)\s*\(", txt)))
+
+
+class MhdError(RuntimeError):
+    def __init__(self, code, what, detail=""):
+        msg = f"{what}: {mhd_status_string(code).decode()} ({code})"
+        super().__init__(msg + (f" [{detail}]" if detail else ""))
+        self.code = code
+
+
+def _ok(code, what, h=None):
+    if code != MHD_OK:
+        detail = mhd_bunch_last_error(h).decode() if h else ""
+        raise MhdError(code, what, detail)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Bunch:
+    """A bunch handle bound to a torch-allocated workspace on the current device.
+
+    dims: (P, 3) interior cells per patch; precision 8 (float64) or 4 (float32).
+    State buffers are flat torch tensors of `state_elems` elements (layout in
+    include/mhd_bunch.h); dt (P,) and dx (P, 3) are float64 device tensors."""
+
+    def __init__(self, dims, g=3, precision=8, gamma=5.0 / 3.0, cfl=0.4, limiter=0,
+                 rho_floor=1e-12, p_floor=1e-12, eps_deg=1e-10, max_scratch_bytes=0,
+                 device="cuda", stream=None):
+        import numpy as np
+        import torch
+        self._dims = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
+        d = mhd_bunch_desc(self._dims.shape[0], self._dims.ctypes.data_as(_ip), g, precision,
+                           gamma, cfl, limiter, rho_floor, p_floor, eps_deg, max_scratch_bytes)
+        h = _h()
+        _ok(mhd_bunch_create(C.byref(h), C.byref(d)), "mhd_bunch_create")
+        self._h = h
+        self.P = int(self._dims.shape[0])
+        self.g = g
+        self.precision = precision
+        self.dtype = torch.float64 if precision == 8 else torch.float32
+        dv = torch.device(device)
+        if dv.type == "cuda" and dv.index is None:
+            dv = torch.device("cuda", torch.cuda.current_device())
+        self.device = dv
+        self.state_elems = int(mhd_bunch_state_elems(h))
+        self.workspace = torch.empty(int(mhd_bunch_workspace_bytes(h)), dtype=torch.uint8,
+                                     device=self.device)
+        assert self.workspace.data_ptr() % 256 == 0
+        _ok(mhd_bunch_bind(h, _ptr(self.workspace), _stream(stream)), "mhd_bunch_bind", h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            mhd_bunch_destroy(h)
+            self._h = None
+
+    def new_state(self):
+        import torch
+        return torch.zeros(self.state_elems, dtype=self.dtype, device=self.device)
+
+    def patch_offset(self, p):
+        return int(mhd_bunch_patch_offset(self._h, p))
+
+    def _check_state(self, U):
+        assert U.is_contiguous() and U.dtype == self.dtype and U.numel() == self.state_elems
+        assert U.device == self.device
+
+    def update(self, U_in, U_out, dt, dx, stream=None):
+        self._check_state(U_in)
+        self._check_state(U_out)
+        _ok(mhd_bunch_update(self._h, _ptr(U_in), _ptr(U_out), _ptr(dt), _ptr(dx), _stream(stream)),
+            "mhd_bunch_update", self._h)
+
+    def cfl(self, U, dx, dt_out, global_min=False, stream=None):
+        self._check_state(U)
+        _ok(mhd_bunch_cfl(self._h, _ptr(U), _ptr(dx), _ptr(dt_out), int(bool(global_min)),
+                          _stream(stream)), "mhd_bunch_cfl", self._h)
+
+    def fill_guards(self, U, nbr, stream=None):
+        self._check_state(U)
+        _ok(mhd_bunch_fill_guards(self._h, _ptr(U), _ptr(nbr), _stream(stream)),
+            "mhd_bunch_fill_guards", self._h)
+
+    def check(self, stream=None):
+        return mhd_bunch_check(self._h, _stream(stream))
+
+    def profile(self, enable=True):
+        _ok(mhd_bunch_profile(self._h, int(bool(enable))), "mhd_bunch_profile")
+
+    def profile_read(self):
+        """{kernel: (total_ms, launches)} recorded since profile(True)."""
+        out = {}
+        for name, k in KERNELS.items():
+            ms = C.c_double()
+            n = C.c_int64()
+            _ok(mhd_bunch_profile_read(self._h, k, C.byref(ms), C.byref(n)),
+                "mhd_bunch_profile_read")
+            out[name] = (ms.value, n.value)
+        return out

@@ -1,0 +1,211 @@
+// mhd_physics.hpp -- pointwise building blocks of the ideal-MHD update, device side.
+//
+// Templated on the element type (float or double).  Everything here is a pure function
+// of its arguments: slope limiter, fast magnetosonic speed, the primitive-variable time
+// derivative used by the half-step predictor, the HLLD Riemann flux and the four-state
+// edge EMF.  Code units with mu_0 = 1 (the energy relation of the paper's §2.1).
+#pragma once
+
+namespace mhd {
+
+// type-exact elementary functions (no silent promotion of float arguments to double)
+__host__ __device__ __forceinline__ float m_abs(float x) { return fabsf(x); }
+__host__ __device__ __forceinline__ double m_abs(double x) { return fabs(x); }
+__host__ __device__ __forceinline__ float m_min(float a, float b) { return fminf(a, b); }
+__host__ __device__ __forceinline__ double m_min(double a, double b) { return fmin(a, b); }
+__host__ __device__ __forceinline__ float m_max(float a, float b) { return fmaxf(a, b); }
+__host__ __device__ __forceinline__ double m_max(double a, double b) { return fmax(a, b); }
+__host__ __device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__host__ __device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+
+template <typename T>
+struct Consts {
+  T gamma;      // adiabatic index
+  T gm1;        // gamma - 1
+  T inv_gm1;    // 1 / (gamma - 1)
+  T rho_floor;  // floors applied to every reconstructed state
+  T p_floor;
+  T eps_deg;    // relative threshold of the HLLD degeneracy switch
+  T tiny;       // guard of the EMF denominators
+  int limiter;  // 0 monotonised central, 1 minmod
+};
+
+// Limited slope from the backward and forward differences (§2.1 "The MUSCL Scheme": the
+// slope estimate must suppress oscillations).  Zero unless both differences share a
+// strict sign; MC = min(2|dm|, 2|dp|, |dm+dp|/2), minmod = min(|dm|, |dp|).
+template <typename T>
+__host__ __device__ __forceinline__ T limited_slope(T dm, T dp, int kind) {
+  if (!(dm * dp > T(0))) return T(0);
+  const T am = m_abs(dm), ap = m_abs(dp);
+  T mag = m_min(am, ap);
+  if (kind == 0) mag = m_min(T(2) * mag, T(0.5) * m_abs(dm + dp));
+  return dm > T(0) ? mag : -mag;
+}
+
+// Fast magnetosonic speed along a direction with normal field bn; the radicand is the
+// cancellation-free (a^2 - b^2)^2 + 4 a^2 b_t^2 / rho.
+template <typename T>
+__host__ __device__ __forceinline__ T fast_speed(T rho, T p, T bn, T bt1, T bt2, T gamma) {
+  const T ir = T(1) / rho;
+  const T a2 = gamma * p * ir;
+  const T bt = bt1 * bt1 + bt2 * bt2;
+  const T b2 = (bn * bn + bt) * ir;
+  const T d = a2 - b2;
+  const T rad = d * d + T(4) * a2 * (bt * ir);
+  return m_sqrt(T(0.5) * (a2 + b2 + m_sqrt(rad)));
+}
+
+// d(q)/dt of ideal MHD in primitive variables q = (rho, u, v, w, p, Bx, By, Bz) from
+// spatial derivatives G[d][m] (rows of collapsed directions are zero).  The induction
+// equation is taken in its div B = 0 form.  Forward-Euler half step of the predictor.
+template <typename T>
+__host__ __device__ __forceinline__ void prim_rate(const T q[8], const T G[3][8], T gamma,
+                                                   T r[8]) {
+  const T rho = q[0], p = q[4];
+  const T ir = T(1) / rho;
+  const T div = G[0][1] + G[1][2] + G[2][3];
+  T ar = T(0), ap = T(0);
+  for (int d = 0; d < 3; ++d) {
+    ar += q[1 + d] * G[d][0];
+    ap += q[1 + d] * G[d][4];
+  }
+  r[0] = -(ar + rho * div);
+  r[4] = -(ap + gamma * p * div);
+  for (int i = 0; i < 3; ++i) {
+    T adv = T(0), ten = T(0), str = T(0), advb = T(0);
+    for (int d = 0; d < 3; ++d) {
+      adv += q[1 + d] * G[d][1 + i];
+      ten += q[5 + d] * G[d][5 + i];
+      str += q[5 + d] * G[d][1 + i];
+      advb += q[1 + d] * G[d][5 + i];
+    }
+    const T grad = G[i][4] + (q[5] * G[i][5] + q[6] * G[i][6] + q[7] * G[i][7]);
+    r[1 + i] = -adv - (grad - ten) * ir;
+    r[5 + i] = str - advb - q[5 + i] * div;
+  }
+}
+
+// HLLD flux through a face (§2.1 "HLLD Solver", Fig. 1; Miyoshi & Kusano 2005).
+// s[0] = left, s[1] = right state in the face frame: (rho, u_n, u_t1, u_t2, p, B_t1, B_t2);
+// bn = shared normal field.  F = (rho, m_n, m_t1, m_t2, E) flux.  The region containing the
+// face is found from the wave fan S_L < S*_L < S_M < S*_R < S_R; its flux is accumulated as
+// F_a + S_a (U*_a - U_a) [+ S*_a (U**_a - U*_a)] on the side a of the contact.
+template <typename T>
+__host__ __device__ __forceinline__ void hlld_flux(const T s[2][7], T bn, const Consts<T>& c,
+                                                   T F[5]) {
+  const T bn2 = bn * bn;
+  T pt[2], en[2], ub[2], cf[2];
+  for (int k = 0; k < 2; ++k) {
+    const T r = s[k][0], u = s[k][1], v = s[k][2], w = s[k][3], p = s[k][4];
+    const T by = s[k][5], bz = s[k][6];
+    const T b2 = bn2 + by * by + bz * bz;
+    pt[k] = p + T(0.5) * b2;
+    en[k] = p * c.inv_gm1 + T(0.5) * r * (u * u + v * v + w * w) + T(0.5) * b2;
+    ub[k] = u * bn + v * by + w * bz;
+    cf[k] = fast_speed(r, p, bn, by, bz, c.gamma);
+  }
+  const T cmx = m_max(cf[0], cf[1]);
+  const T S[2] = {m_min(s[0][1], s[1][1]) - cmx, m_max(s[0][1], s[1][1]) + cmx};
+  const T sd[2] = {S[0] - s[0][1], S[1] - s[1][1]};     // S_a - u_a
+  const T mf[2] = {sd[0] * s[0][0], sd[1] * s[1][0]};   // rho_a (S_a - u_a)
+  const T iden = T(1) / (mf[1] - mf[0]);
+  const T sm = (mf[1] * s[1][1] - mf[0] * s[0][1] - pt[1] + pt[0]) * iden;
+  const T pts = (mf[1] * pt[0] - mf[0] * pt[1] + mf[0] * mf[1] * (s[1][1] - s[0][1])) * iden;
+
+  // single-star states
+  T rs[2], vs[2], ws[2], bys[2], bzs[2], es[2], ubs[2];
+  for (int k = 0; k < 2; ++k) {
+    const T isd = T(1) / (S[k] - sm);
+    rs[k] = mf[k] * isd;
+    const T dd = mf[k] * (S[k] - sm) - bn2;
+    const T qq = mf[k] * sd[k] - bn2;
+    if (m_abs(dd) > c.eps_deg * (mf[k] * sd[k] + bn2)) {
+      const T idd = T(1) / dd;
+      const T tv = bn * (sm - s[k][1]) * idd;
+      const T tb = qq * idd;
+      vs[k] = s[k][2] - s[k][5] * tv;
+      ws[k] = s[k][3] - s[k][6] * tv;
+      bys[k] = s[k][5] * tb;
+      bzs[k] = s[k][6] * tb;
+    } else {
+      vs[k] = s[k][2];
+      ws[k] = s[k][3];
+      bys[k] = s[k][5];
+      bzs[k] = s[k][6];
+    }
+    ubs[k] = sm * bn + vs[k] * bys[k] + ws[k] * bzs[k];
+    es[k] = (sd[k] * en[k] - pt[k] * s[k][1] + pts * sm + bn * (ub[k] - ubs[k])) * isd;
+  }
+
+  // rotational (Alfven) discontinuities and the double-star state
+  const T sq[2] = {m_sqrt(rs[0]), m_sqrt(rs[1])};
+  const T abn = m_abs(bn);
+  const T Ss[2] = {sm - abn / sq[0], sm + abn / sq[1]};
+  const T sg = bn < T(0) ? T(-1) : T(1);
+  const T isum = T(1) / (sq[0] + sq[1]);
+  const T vss = (sq[0] * vs[0] + sq[1] * vs[1] + (bys[1] - bys[0]) * sg) * isum;
+  const T wss = (sq[0] * ws[0] + sq[1] * ws[1] + (bzs[1] - bzs[0]) * sg) * isum;
+  const T byss = (sq[0] * bys[1] + sq[1] * bys[0] + sq[0] * sq[1] * (vs[1] - vs[0]) * sg) * isum;
+  const T bzss = (sq[0] * bzs[1] + sq[1] * bzs[0] + sq[0] * sq[1] * (ws[1] - ws[0]) * sg) * isum;
+  const T ubss = sm * bn + vss * byss + wss * bzss;
+
+  // region of the face and the side it belongs to
+  int reg;
+  if (S[0] > T(0)) reg = 0;
+  else if (Ss[0] >= T(0)) reg = 1;
+  else if (sm >= T(0)) reg = 2;
+  else if (Ss[1] >= T(0)) reg = 3;
+  else if (S[1] >= T(0)) reg = 4;
+  else reg = 5;
+  const int k = reg <= 2 ? 0 : 1;
+  const T r = s[k][0], u = s[k][1], v = s[k][2], w = s[k][3];
+  const T by = s[k][5], bz = s[k][6];
+  F[0] = r * u;
+  F[1] = r * u * u + pt[k] - bn2;
+  F[2] = r * v * u - by * bn;
+  F[3] = r * w * u - bz * bn;
+  F[4] = u * (en[k] + pt[k]) - bn * ub[k];
+  if (reg >= 1 && reg <= 4) {
+    const T Us[5] = {rs[k], rs[k] * sm, rs[k] * vs[k], rs[k] * ws[k], es[k]};
+    const T Uo[5] = {r, r * u, r * v, r * w, en[k]};
+    T Fs[5];
+    for (int m = 0; m < 5; ++m) Fs[m] = F[m] + S[k] * (Us[m] - Uo[m]);
+    if (reg == 2 || reg == 3) {
+      const T ess = k == 0 ? es[0] - sq[0] * (ubs[0] - ubss) * sg
+                           : es[1] + sq[1] * (ubs[1] - ubss) * sg;
+      const T Uss[5] = {rs[k], rs[k] * sm, rs[k] * vss, rs[k] * wss, ess};
+      for (int m = 0; m < 5; ++m) Fs[m] = Fs[m] + Ss[k] * (Uss[m] - Us[m]);
+    }
+    for (int m = 0; m < 5; ++m) F[m] = Fs[m];
+  }
+}
+
+// Edge EMF from the four predicted corner states around an edge (§2.1 "Constrained
+// transport and 2D-extension", Fig. 3: SW/SE/NW/NE).  Each corner C = (rho, u_a, u_b, p,
+// B_e, B_a, B_b) for the edge direction e and its cyclic transverse pair (a, b); W/E are
+// the low/high a sides, S/N the low/high b sides.  Two one-dimensional HLL fluxes of the
+// transverse field, composed, with outer speeds bounded over the four corners.
+template <typename T>
+__host__ __device__ __forceinline__ T uct_emf(const T C[4][7], const Consts<T>& c) {
+  T emf[4];
+  T apa = T(0), ama = T(0), apb = T(0), amb = T(0);
+  for (int k = 0; k < 4; ++k) {
+    const T r = C[k][0], ua = C[k][1], ubb = C[k][2], p = C[k][3];
+    const T be = C[k][4], ba = C[k][5], bb = C[k][6];
+    emf[k] = ua * bb - ubb * ba;
+    const T cfa = fast_speed(r, p, ba, bb, be, c.gamma);
+    const T cfb = fast_speed(r, p, bb, be, ba, c.gamma);
+    apa = m_max(apa, ua + cfa);
+    ama = m_max(ama, cfa - ua);
+    apb = m_max(apb, ubb + cfb);
+    amb = m_max(amb, cfb - ubb);
+  }
+  const T da = m_max(apa + ama, c.tiny);
+  const T db = m_max(apb + amb, c.tiny);
+  // corners: 0 SW, 1 SE, 2 NW, 3 NE
+  const T avg = (apa * apb * emf[0] + apa * amb * emf[2] + ama * apb * emf[1] + ama * amb * emf[3]) /
+                (da * db);
+  return avg - apa * ama / da * (C[1][6] - C[0][6]) + apb * amb / db * (C[2][5] - C[0][5]);
+}
+
+}  // namespace mhd

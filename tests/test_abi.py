@@ -1,0 +1,100 @@
+"""The C-ABI library loads, exports every function include/mhd_bunch.h declares, and
+validates descriptions on the host (mhd_bunch_create touches no device)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2508_09568_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2508_09568_amd import binding
+    return binding
+
+
+def test_one_hip_runtime_in_the_process(B):
+    assert len(B._hip_runtimes()) == 1
+
+
+def test_library_exports_every_declared_symbol(B):
+    names = B.header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(B._lib, n), n
+
+
+def _desc(B, dims, **kw):
+    dims = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
+    base = dict(guard=3, precision=8, gamma=5 / 3, cfl=0.4, limiter=0, rho_floor=1e-12,
+                p_floor=1e-12, eps_deg=1e-10, max_scratch_bytes=0)
+    base.update(kw)
+    d = B.mhd_bunch_desc(dims.shape[0], dims.ctypes.data_as(C.POINTER(C.c_int32)), base["guard"],
+                         base["precision"], base["gamma"], base["cfl"], base["limiter"],
+                         base["rho_floor"], base["p_floor"], base["eps_deg"],
+                         base["max_scratch_bytes"])
+    return d, dims
+
+
+def _create(B, dims, **kw):
+    d, keep = _desc(B, dims, **kw)
+    h = C.c_void_p()
+    rc = B.mhd_bunch_create(C.byref(h), C.byref(d))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw,dims", [
+    (dict(guard=2), [[16, 16, 16]]),          # stencil needs three guard layers
+    (dict(precision=2), [[16, 16, 16]]),
+    (dict(gamma=1.0), [[16, 16, 16]]),
+    (dict(limiter=3), [[16, 16, 16]]),
+    (dict(), [[2, 16, 16]]),                  # an active direction narrower than g
+    (dict(), [[16, 0, 16]]),
+    (dict(rho_floor=0.0), [[16, 16, 16]]),
+])
+def test_create_rejects_invalid_descriptions(B, kw, dims):
+    rc, h = _create(B, dims, **kw)
+    assert rc == B.MHD_EINVAL and not h.value
+
+
+def test_mixed_dimensionality_is_unsupported(B):
+    rc, h = _create(B, [[16, 16, 16], [16, 16, 1]])
+    assert rc == B.MHD_EUNSUPPORTED
+
+
+def test_sizes_and_offsets_match_the_layout(B):
+    w = W.uneven(mix=((9, 3), (13, 2)), nsteps=1)
+    L = w.layout
+    rc, h = _create(B, L.dims, precision=4)
+    assert rc == B.MHD_OK
+    try:
+        assert B.mhd_bunch_state_elems(h) == L.total
+        assert B.mhd_bunch_state_bytes(h) == 4 * L.total
+        for p in range(L.P):
+            assert B.mhd_bunch_patch_offset(h, p) == L.base[p]
+        assert B.mhd_bunch_patch_offset(h, L.P) == -1
+        assert B.mhd_bunch_workspace_bytes(h) > 0
+        # calls that need a bound workspace refuse before touching the device
+        assert B.mhd_bunch_update(h, C.c_void_p(256), C.c_void_p(512), C.c_void_p(768),
+                                  C.c_void_p(1024), None) == B.MHD_ESTATE
+    finally:
+        B.mhd_bunch_destroy(h)
+
+
+def test_scratch_cap_bounds_the_workspace(B):
+    dims = [[16, 16, 16]] * 8
+    rc, h1 = _create(B, dims)
+    rc2, h2 = _create(B, dims, max_scratch_bytes=4 << 20)
+    assert rc == rc2 == B.MHD_OK
+    try:
+        assert B.mhd_bunch_workspace_bytes(h2) < B.mhd_bunch_workspace_bytes(h1)
+        assert B.mhd_bunch_workspace_bytes(h2) < (6 << 20)
+    finally:
+        B.mhd_bunch_destroy(h1)
+        B.mhd_bunch_destroy(h2)
+
+
+def test_status_strings(B):
+    for code in range(-6, 1):
+        assert B.mhd_status_string(code)

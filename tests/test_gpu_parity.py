@@ -1,0 +1,327 @@
+"""GPU parity of the HIP path (called through the C ABI) against the FP64 oracle.
+
+Per-step bar (FP64): per-field relative max-norm difference <= 1e-12 from identical U^n
+and dt.  FP32: L1 relative difference against the FP64 oracle after full runs, with the
+oracle's dt sequence fed in.  Full-size workloads are checked on sampled patches that
+the oracle recomputes one by one from the GPU's own guard-filled input."""
+import math
+
+import numpy as np
+import pytest
+
+import mhdtest as mt
+from gpu_util import dev, host, l1_rel_fields, log, make_bunch, rel_err_fields
+from paper_2508_09568_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_STEP_TOL = 1e-12
+
+
+def _case(name):
+    import oracle
+    if name == "sod":
+        w = W.sod(128)
+        L, U, dx, nbr, gam = w.layout, w.U, w.dx, w.nbr, w.gamma
+    elif name == "sod8":
+        w = W.sod(128, patches=8)
+        L, U, dx, nbr, gam = w.layout, w.U, w.dx, w.nbr, w.gamma
+    elif name == "ot64":
+        w = W.orszag_tang(64, 32)
+        L, U, dx, nbr, gam = w.layout, w.U, w.dx, w.nbr, w.gamma
+    elif name == "wave2d_yz":
+        L0, U0, dx0, _, _ = mt.linear_wave_2d(32, "fast", amp=0.1)
+        U, L, dx, grid = mt.cyclic_permute(U0, L0, dx0, (2, 2, 1), 1)
+        nbr = W.grid_neighbours(grid, (True, True, True))
+        gam = 5 / 3
+    elif name == "wave2d_zx":
+        L0, U0, dx0, _, _ = mt.linear_wave_2d(32, "alfven", amp=0.1)
+        U, L, dx, grid = mt.cyclic_permute(U0, L0, dx0, (2, 2, 1), 2)
+        nbr = W.grid_neighbours(grid, (True, True, True))
+        gam = 5 / 3
+    elif name == "wave1d_z":
+        L0, U0, dx0, _, _ = mt.linear_wave_1d(64, "slow", amp=0.1)
+        U, L, dx, grid = mt.cyclic_permute(U0, L0, dx0, (1, 1, 1), 2)
+        nbr = W.grid_neighbours(grid, (True, True, True))
+        gam = 5 / 3
+    elif name == "turb3d":
+        w = W.turbulence(N=32, patch=16)
+        L, U, dx, nbr, gam = w.layout, w.U.numpy(), w.dx, w.nbr, w.gamma
+    elif name == "ragged3d":
+        w = W.uneven(mix=((9, 3), (13, 2), (20, 2)))
+        L, U, dx, nbr, gam = w.layout, w.U.numpy(), w.dx, None, w.gamma
+    elif name == "adjoint32":
+        w = W.adjoint_case(N=32, patch=16)
+        L, U, dx, nbr, gam = w.layout, w.U, w.dx, w.nbr, w.gamma
+    else:
+        raise KeyError(name)
+    U = np.ascontiguousarray(U, dtype=np.float64).copy()
+    if nbr is not None:
+        oracle.fill_guards(U, L.dims, L.g, nbr)
+    return L, U, np.ascontiguousarray(dx, dtype=np.float64), nbr, gam
+
+
+STEP_CASES = ["sod", "sod8", "ot64", "wave2d_yz", "wave2d_zx", "wave1d_z", "turb3d", "ragged3d",
+              "adjoint32"]
+
+
+@pytest.mark.parametrize("name", STEP_CASES)
+def test_step_parity_fp64(name):
+    import oracle
+    log(f"[gpu] step parity fp64 case={name}")
+    L, U, dx, nbr, gam = _case(name)
+    prm = oracle.Params(gamma=gam)
+    dt = oracle.cfl_many(U, L.dims, L.g, dx, prm)
+    dt = np.full(L.P, dt.min()) if nbr is not None else dt     # local dt when guards are frozen
+    ref = oracle.step_many(U, L.dims, L.g, dt, dx, prm)
+    B = make_bunch(L, gam)
+    Ui = dev(U)
+    Uo = dev(np.zeros_like(U))
+    B.update(Ui, Uo, dev(dt), dev(dx))
+    assert B.check() == 0
+    err = rel_err_fields(L, host(Uo), ref)
+    log(f"    per-field rel err {err}")
+    assert np.all(err <= FP64_STEP_TOL), err
+
+
+@pytest.mark.parametrize("name", ["sod", "sod8", "ot64", "wave2d_yz", "turb3d", "adjoint32"])
+def test_guard_fill_matches_oracle_bitwise(name):
+    import oracle
+    log(f"[gpu] guard fill case={name}")
+    L, U, dx, nbr, gam = _case(name)
+    S = U.copy()
+    for p in range(L.P):          # scramble every guard, keep owned data
+        keep = L.interior(S, p).copy()
+        L.view(S, p)[:] = -3.25
+        L.interior(S, p)[:] = keep
+    ref = oracle.fill_guards(S.copy(), L.dims, L.g, nbr)
+    B = make_bunch(L, gam)
+    Ud = dev(S)
+    B.fill_guards(Ud, dev(nbr.astype(np.int32)))
+    assert B.check() == 0
+    assert np.array_equal(host(Ud), ref)
+
+
+@pytest.mark.parametrize("name", ["sod", "ot64", "turb3d", "ragged3d"])
+def test_cfl_matches_oracle(name):
+    import oracle
+    import torch
+    log(f"[gpu] cfl case={name}")
+    L, U, dx, nbr, gam = _case(name)
+    ref = oracle.cfl_many(U, L.dims, L.g, dx, oracle.Params(gamma=gam))
+    B = make_bunch(L, gam)
+    dt = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    B.cfl(dev(U), dev(dx), dt)
+    got = host(dt)
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=0)
+    B.cfl(dev(U), dev(dx), dt, global_min=True)
+    assert np.all(host(dt) == got.min())
+
+
+def _gpu_run(B, L, U, dx, nbr, t_end=None, nsteps=None, dt_seq=None):
+    """GPU driver: fill guards, global dt (or the given sequence), update, swap."""
+    import torch
+    Ua, Ub = dev(U), dev(np.zeros_like(U))
+    if B.precision == 4:
+        Ua, Ub = Ua.float(), Ub.float()
+    dxd = dev(dx)
+    nb = dev(nbr.astype(np.int32)) if nbr is not None else None
+    dt = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    t, k, dts = 0.0, 0, []
+    while True:
+        if nsteps is not None and k >= nsteps:
+            break
+        if t_end is not None and t >= t_end * (1 - 1e-14):
+            break
+        if nb is not None:
+            B.fill_guards(Ua, nb)
+        if dt_seq is not None:
+            d = float(dt_seq[k])
+        else:
+            B.cfl(Ua, dxd, dt, global_min=True)
+            d = float(host(dt)[0])
+            if t_end is not None and t + d > t_end:
+                d = t_end - t
+        dt.fill_(d)
+        B.update(Ua, Ub, dt, dxd)
+        Ua, Ub = Ub, Ua
+        t += d
+        k += 1
+        dts.append(d)
+    if nb is not None:
+        B.fill_guards(Ua, nb)
+    assert B.check() == 0
+    return host(Ua), np.array(dts)
+
+
+def test_sod_full_run_fp64_matches_oracle():
+    import oracle
+    log("[gpu] sod full run fp64")
+    L, U, dx, nbr, gam = _case("sod")
+    ref, dref = oracle.run(U, L.dims, L.g, dx, nbr, oracle.Params(gamma=gam), t_end=0.2,
+                           record_dt=True)
+    got, dts = _gpu_run(make_bunch(L, gam), L, U, dx, nbr, t_end=0.2)
+    assert len(dts) == len(dref)
+    np.testing.assert_allclose(dts, dref, rtol=1e-12)
+    err = rel_err_fields(L, got, ref)
+    log(f"    rel err after {len(dts)} steps {err}")
+    assert np.all(err <= 1e-10)
+
+
+def test_orszag_tang_run_fp64_matches_oracle():
+    import oracle
+    log("[gpu] OT 64^2 100 steps fp64")
+    L, U, dx, nbr, gam = _case("ot64")
+    ref, dref = oracle.run(U, L.dims, L.g, dx, nbr, oracle.Params(gamma=gam), nsteps=100,
+                           record_dt=True)
+    got, dts = _gpu_run(make_bunch(L, gam), L, U, dx, nbr, nsteps=100)
+    np.testing.assert_allclose(dts, dref, rtol=1e-11)
+    err = rel_err_fields(L, got, ref)
+    log(f"    rel err after 100 steps {err}")
+    assert np.all(err <= 1e-10)
+
+
+@pytest.mark.parametrize("name,t_end,tol", [("sod", 0.2, 2e-6), ("ot64", 0.5, 1e-4)])
+def test_fp32_full_run_against_fp64_oracle(name, t_end, tol):
+    import oracle
+    log(f"[gpu] fp32 full run case={name} t_end={t_end}")
+    L, U, dx, nbr, gam = _case(name)
+    ref, dref = oracle.run(U, L.dims, L.g, dx, nbr, oracle.Params(gamma=gam), t_end=t_end,
+                           record_dt=True)
+    got, _ = _gpu_run(make_bunch(L, gam, precision=4), L, U, dx, nbr, dt_seq=dref,
+                      nsteps=len(dref))
+    l1 = l1_rel_fields(L, got, ref)
+    log(f"    FP32 L1 rel err per field after {len(dref)} steps: {l1}")
+    assert np.all(l1 <= tol), l1
+
+
+def test_conservation_and_divergence_on_gpu():
+    # 64^3 periodic (2^3 patches of 32^3): resolved enough that the rms Mach-4 field stays
+    # physical (at 32^3 it develops p <= 0 cells after four steps, in the oracle too)
+    log("[gpu] conservation turbulence 64^3 fp64")
+    w = W.turbulence(N=64, patch=32)
+    L, U, dx, nbr, gam = w.layout, w.U.numpy().copy(), w.dx, w.nbr, w.gamma
+    import oracle
+    oracle.fill_guards(U, L.dims, L.g, nbr)
+    s0 = mt.sums(U, L)
+    d0 = mt.div_b(U, L, dx)
+    got, _ = _gpu_run(make_bunch(L, gam), L, U, dx, nbr, nsteps=5)
+    s1 = mt.sums(got, L)
+    scale = mt.sums(np.abs(U), L) + 1.0
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * scale)
+    for a, b in zip(d0, mt.div_b(got, L, dx)):
+        assert np.abs(b - a).max() * (1.0 / 64) <= 1e-13
+
+
+def test_update_is_deterministic():
+    log("[gpu] determinism ragged3d")
+    L, U, dx, nbr, gam = _case("ragged3d")
+    B = make_bunch(L, gam)
+    dt = dev(np.full(L.P, 1e-4))
+    outs = []
+    for _ in range(2):
+        Uo = dev(np.zeros_like(U))
+        B.update(dev(U), Uo, dt, dev(dx))
+        outs.append(host(Uo))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_chunked_scratch_gives_identical_results():
+    log("[gpu] chunked scratch turb3d")
+    L, U, dx, nbr, gam = _case("turb3d")
+    dt = dev(np.full(L.P, 1e-4))
+    outs = []
+    for cap in (0, 3 << 20):
+        B = make_bunch(L, gam, max_scratch_bytes=cap)
+        Uo = dev(np.zeros_like(U))
+        B.update(dev(U), Uo, dt, dev(dx))
+        outs.append(host(Uo))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_nonphysical_state_is_reported():
+    log("[gpu] non-physical flag")
+    L, U, dx, nbr, gam = _case("ot64")
+    U = U.copy()
+    V = L.view(U, 1)
+    V[4, 0, 10, 10] = -1.0                     # negative total energy -> p < 0
+    B = make_bunch(L, gam)
+    Uo = dev(np.zeros_like(U))
+    B.update(dev(U), Uo, dev(np.full(L.P, 1e-4)), dev(dx))
+    from paper_2508_09568_amd.binding import MHD_ENONPHYS
+    assert B.check() == MHD_ENONPHYS
+    assert B.check() == 0                      # the flag is cleared by the check
+
+
+def _sampled_parity(w, precision, samples, dt_local, tol):
+    """One update of a full-size workload on the GPU; the oracle recomputes the sampled
+    patches from the GPU's own input (guards included)."""
+    import oracle
+    import torch
+    L = w.layout
+    prm = oracle.Params(gamma=w.gamma)
+    B = make_bunch(L, w.gamma, precision=precision)
+    dtype = torch.float64 if precision == 8 else torch.float32
+    Ui = w.U.to(device="cuda", dtype=dtype)
+    dxd = dev(w.dx)
+    if w.nbr is not None:
+        B.fill_guards(Ui, dev(w.nbr.astype(np.int32)))
+    dt = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    B.cfl(Ui, dxd, dt, global_min=not dt_local)
+    Uo = torch.empty_like(Ui)
+    B.update(Ui, Uo, dt, dxd)
+    assert B.check() == 0
+    dth = host(dt)
+    worst = np.zeros(8)
+    for p in samples:
+        a, b = int(L.base[p]), int(L.base[p + 1])
+        Up = Ui[a:b].double().cpu().numpy()
+        n = L.dims[p]
+        ref = oracle.step_many(Up, n[None], L.g, [dth[p]], w.dx[p][None], prm)
+        got = Uo[a:b].double().cpu().numpy()
+        Lp = W.Layout(n[None], L.g)
+        worst = np.maximum(worst, rel_err_fields(Lp, got, ref))
+    del Ui, Uo, B
+    torch.cuda.empty_cache()
+    log(f"    sampled per-field rel err {worst}")
+    assert np.all(worst <= tol), worst
+
+
+def test_turbulence_512_full_size_sampled_fp64():
+    log("[gpu] turbulence 512^3 (4096 x 32^3) fp64, sampled patches")
+    w = W.turbulence(device="cuda")
+    _sampled_parity(w, 8, [0, 1, 2047, 4095], dt_local=False, tol=FP64_STEP_TOL)
+
+
+def test_turbulence_512_full_size_sampled_fp32():
+    log("[gpu] turbulence 512^3 (4096 x 32^3) fp32, sampled patches vs fp64 oracle")
+    w = W.turbulence(device="cuda", dtype=None)
+    _sampled_parity(w, 4, [0, 1234, 4095], dt_local=False, tol=2e-5)
+
+
+def test_uneven_full_size_sampled_fp64():
+    log("[gpu] uneven 3600 patches fp64, local dt, sampled patches of every size")
+    w = W.uneven(device="cuda")
+    dims = w.layout.dims[:, 0]
+    samples = []
+    for n in (16, 24, 32, 48):
+        idx = np.nonzero(dims == n)[0]
+        samples += [int(idx[0]), int(idx[-1])]
+    _sampled_parity(w, 8, samples, dt_local=True, tol=FP64_STEP_TOL)
+
+
+def test_adjoint_case_20_steps_fp64():
+    import oracle
+    log("[gpu] adjoint case 64^3 (8 x 32^3) fp64, 20 steps at fixed dt")
+    w = W.adjoint_case()
+    L = w.layout
+    U = w.U.copy()
+    oracle.fill_guards(U, L.dims, L.g, w.nbr)
+    prm = oracle.Params(gamma=w.gamma)
+    dt0 = float(oracle.cfl_many(U, L.dims, L.g, w.dx, prm).min())
+    ref = oracle.run(U, L.dims, L.g, w.dx, w.nbr, prm, nsteps=20, dt_fixed=dt0)
+    got, _ = _gpu_run(make_bunch(L, w.gamma), L, U, w.dx, w.nbr, nsteps=20,
+                      dt_seq=np.full(20, dt0))
+    err = rel_err_fields(L, got, ref)
+    log(f"    rel err after 20 steps {err}")
+    assert np.all(err <= 1e-11)
