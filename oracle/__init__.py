@@ -75,6 +75,12 @@ def lib():
         L.mhd_oracle_step_jvp.argtypes = [ip, C.c_int32, dp, dp, dp, dp, C.c_double, dp, P(_Params)]
         L.mhd_oracle_step_jvp_many.argtypes = [C.c_int32, ip, C.c_int32, dp, dp, dp, dp, dp, dp,
                                                P(_Params)]
+        up = P(C.c_uint64)
+        L.mhd_oracle_step_sig_many.argtypes = [C.c_int32, ip, C.c_int32, dp, dp, dp, dp,
+                                               P(_Params), up]
+        L.mhd_oracle_step_ext_many.argtypes = [C.c_int32, ip, C.c_int32, C.c_void_p, C.c_void_p,
+                                               dp, dp, P(_Params), up]
+        L.mhd_oracle_fill_guards_ext.argtypes = [C.c_int32, ip, C.c_int32, C.c_void_p, ip]
         L.mhd_oracle_count_ops.argtypes = [ip, C.c_int32, dp, C.c_double, dp, P(_Params), lp]
         L.mhd_oracle_hlld.argtypes = [dp, dp, P(_Params), dp, ip]
         L.mhd_oracle_cfast.argtypes = [C.c_double] * 6
@@ -128,6 +134,54 @@ def step_many(U, dims, g, dt, dx, prm: Params, count_floors=False):
     if rc != 0:
         raise ValueError("mhd_oracle_step_many: invalid argument")
     return (out, nf) if count_floors else out
+
+
+def step_sig_many(U, dims, g, dt, dx, prm: Params):
+    """step_many (bitwise the same U_out) plus each patch's branch signature, a uint64
+    hash of every comparison outcome of its update."""
+    U = _f64(U)
+    dims = _i32(dims).reshape(-1, 3)
+    P = dims.shape[0]
+    dt = _f64(np.broadcast_to(np.asarray(dt, dtype=np.float64), (P,)))
+    dx = _f64(np.broadcast_to(np.asarray(dx, dtype=np.float64), (P, 3)))
+    out = np.empty_like(U)
+    sig = np.zeros(P, dtype=np.uint64)
+    p = prm.c()
+    rc = lib().mhd_oracle_step_sig_many(P, _i(dims), g, _d(U), _d(out), _d(dt), _d(dx),
+                                        C.byref(p), sig.ctypes.data_as(C.POINTER(C.c_uint64)))
+    if rc != 0:
+        raise ValueError("mhd_oracle_step_sig_many: invalid argument")
+    return out, sig
+
+
+def step_ext_many(U, dims, g, dt, dx, prm: Params):
+    """One update in x87 extended precision: U is np.longdouble; returns (U_out, per-patch
+    branch signatures).  Same scheme and FP64 parameters as step_many."""
+    assert U.dtype == np.longdouble and np.finfo(np.longdouble).nmant >= 63
+    U = np.ascontiguousarray(U)
+    dims = _i32(dims).reshape(-1, 3)
+    P = dims.shape[0]
+    dt = _f64(np.broadcast_to(np.asarray(dt, dtype=np.float64), (P,)))
+    dx = _f64(np.broadcast_to(np.asarray(dx, dtype=np.float64), (P, 3)))
+    out = np.empty_like(U)
+    sig = np.zeros(P, dtype=np.uint64)
+    p = prm.c()
+    rc = lib().mhd_oracle_step_ext_many(P, _i(dims), g, U.ctypes.data, out.ctypes.data, _d(dt),
+                                        _d(dx), C.byref(p),
+                                        sig.ctypes.data_as(C.POINTER(C.c_uint64)))
+    if rc != 0:
+        raise ValueError("mhd_oracle_step_ext_many: invalid argument")
+    return out, sig
+
+
+def fill_guards_ext(U, dims, g, nbr):
+    """fill_guards on an np.longdouble state."""
+    assert U.dtype == np.longdouble and U.flags.c_contiguous
+    dims = _i32(dims).reshape(-1, 3)
+    nbr = _i32(nbr).reshape(-1, 27)
+    if lib().mhd_oracle_fill_guards_ext(dims.shape[0], _i(dims), g, U.ctypes.data, _i(nbr)) != 0:
+        raise ValueError("mhd_oracle_fill_guards_ext: inconsistent neighbour table")
+    return U
 
 
 def cfl_many(U, dims, g, dx, prm: Params):

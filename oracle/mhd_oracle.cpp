@@ -12,7 +12,9 @@
  * The scalar type is a template parameter so the same passes run in
  *   double -- the reference result,
  *   Dual   -- forward-mode derivative at fixed dt (reference gradients),
- *   Cnt    -- counts the arithmetic of one update (algorithmic flops per cell).
+ *   Cnt    -- counts the arithmetic of one update (algorithmic flops per cell),
+ *   TrcT   -- double or x87 extended precision, plus a hash of every branch outcome
+ *             (the branch signature; extended precision serves finite differences).
  *
  * Readings of points the paper leaves open (limiter, predictor, EMF solver, CFL rule,
  * floors, guard width) are listed in the design doc; each function cites what it follows.
@@ -70,6 +72,33 @@ inline bool operator>(Cnt a, Cnt b) { g_ops.cmp++; return a.v > b.v; }
 inline bool operator<=(Cnt a, Cnt b) { g_ops.cmp++; return a.v <= b.v; }
 inline bool operator>=(Cnt a, Cnt b) { g_ops.cmp++; return a.v >= b.v; }
 inline Cnt ssqrt(Cnt a) { g_ops.sqrt++; return Cnt(std::sqrt(a.v)); }
+
+/* Traced value: plain arithmetic in R (double, or x87 extended long double), and every
+ * comparison folds its outcome into a running hash, so two runs that take the same
+ * branches everywhere (limiter cases, min/max and |.| choices, HLLD regions and
+ * degeneracy switch, floors) end with the same hash.  Used to check that the two ends of
+ * a finite difference sit on one smooth branch of the update. */
+thread_local uint64_t g_sig;
+inline bool note(bool b) {
+  g_sig = (g_sig ^ (b ? 0x9e3779b97f4a7c15ull : 0x6a09e667f3bcc909ull)) * 0x100000001b3ull;
+  return b;
+}
+template <class R>
+struct TrcT {
+  R v;
+  TrcT(R a = R(0)) : v(a) {}
+  friend TrcT operator+(TrcT a, TrcT b) { return TrcT(a.v + b.v); }
+  friend TrcT operator-(TrcT a, TrcT b) { return TrcT(a.v - b.v); }
+  friend TrcT operator*(TrcT a, TrcT b) { return TrcT(a.v * b.v); }
+  friend TrcT operator/(TrcT a, TrcT b) { return TrcT(a.v / b.v); }
+  friend TrcT operator-(TrcT a) { return TrcT(-a.v); }
+  friend bool operator<(TrcT a, TrcT b) { return note(a.v < b.v); }
+  friend bool operator>(TrcT a, TrcT b) { return note(a.v > b.v); }
+  friend bool operator<=(TrcT a, TrcT b) { return note(a.v <= b.v); }
+  friend bool operator>=(TrcT a, TrcT b) { return note(a.v >= b.v); }
+  friend TrcT ssqrt(TrcT a) { return TrcT(std::sqrt(a.v)); }
+  friend double val(const TrcT& x) { return double(x.v); }
+};
 
 inline double ssqrt(double a) { return std::sqrt(a); }
 inline double val(double x) { return x; }
@@ -629,6 +658,88 @@ long patch_elems(const int32_t n[3], int g) {
 
 /* ------------------------------------------------------------------ C interface */
 
+template <class E>
+int fill_guards_t(int32_t npatch, const int32_t* dims, int32_t g, E* U, const int32_t* nbr) {
+  if (npatch < 0 || !U || !nbr) return -1;
+  std::vector<Geom> Gs(npatch);
+  std::vector<long> base(npatch + 1, 0);
+  for (int p = 0; p < npatch; ++p) {
+    if (!Gs[p].init(dims + 3 * p, g)) return -1;
+    base[p + 1] = base[p] + 8 * Gs[p].Nc;
+  }
+  int bad = 0;
+  for (int p = 0; p < npatch && !bad; ++p) {
+    const Geom& G = Gs[p];
+    for (int k = 0; k < G.N[2]; ++k)
+      for (int j = 0; j < G.N[1]; ++j)
+        for (int i = 0; i < G.N[0]; ++i) {
+          int idx[3] = {i, j, k}, o[3];
+          bool guard = false;
+          for (int d = 0; d < 3; ++d) {
+            o[d] = 0;
+            if (!G.act[d]) continue;
+            if (idx[d] < g) o[d] = -1;
+            else if (idx[d] >= g + G.n[d]) o[d] = +1;
+            if (o[d]) guard = true;
+          }
+          if (!guard) continue;
+          // directions whose face neighbour is the domain boundary: zero-gradient copy
+          for (int d = 0; d < 3; ++d) {
+            if (!o[d]) continue;
+            int fo[3] = {0, 0, 0};
+            fo[d] = o[d];
+            if (nbr[27 * p + (fo[0] + 1) + 3 * (fo[1] + 1) + 9 * (fo[2] + 1)] < 0) {
+              idx[d] = std::min(std::max(idx[d], g), g + G.n[d] - 1);
+              o[d] = 0;
+            }
+          }
+          int src = p;
+          if (o[0] || o[1] || o[2]) src = nbr[27 * p + (o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1)];
+          if (src < 0 || src >= npatch) { bad = 1; break; }
+          const Geom& H = Gs[src];
+          if (H.n[0] != G.n[0] || H.n[1] != G.n[1] || H.n[2] != G.n[2]) { bad = 1; break; }
+          const long cs = (idx[0] - o[0] * G.n[0]) + H.st[1] * (idx[1] - o[1] * G.n[1]) +
+                          H.st[2] * (idx[2] - o[2] * G.n[2]);
+          const long cd = (long)i + G.st[1] * j + G.st[2] * k;
+          for (int m = 0; m < 8; ++m) U[base[p] + m * G.Nc + cd] = U[base[src] + m * H.Nc + cs];
+        }
+  }
+  return bad ? -1 : 0;
+}
+
+/* one update in arithmetic R with the branch signature (sig may be NULL) */
+template <class R>
+int step_traced(const int32_t n[3], int32_t g, const R* U_in, R* U_out, double dt,
+                const double dx[3], const mhd_oracle_params* prm, uint64_t* sig) {
+  Geom G;
+  if (!G.init(n, g) || !check_params(prm) || !U_in || !U_out || !(dt >= 0.0)) return -1;
+  const long ne = 8 * G.Nc;
+  std::vector<TrcT<R>> a(ne), b(ne);
+  for (long i = 0; i < ne; ++i) a[i] = TrcT<R>(U_in[i]);
+  Stepper<TrcT<R>> s(G, *prm, dt, dx);
+  g_sig = 0xcbf29ce484222325ull;
+  s.run(a.data(), b.data());
+  if (sig) *sig = g_sig;
+  for (long i = 0; i < ne; ++i) U_out[i] = b[i].v;
+  return 0;
+}
+
+template <class R>
+int step_traced_many(int32_t npatch, const int32_t* dims, int32_t g, const R* U_in, R* U_out,
+                     const double* dt, const double* dx, const mhd_oracle_params* prm,
+                     uint64_t* sig) {
+  if (npatch < 0 || !check_params(prm)) return -1;
+  std::vector<long> base(npatch + 1, 0);
+  for (int p = 0; p < npatch; ++p) base[p + 1] = base[p] + patch_elems(dims + 3 * p, g);
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+  for (int p = 0; p < npatch; ++p)
+    if (step_traced(dims + 3 * p, g, U_in + base[p], U_out + base[p], dt[p], dx + 3 * p, prm,
+                    sig ? sig + p : nullptr))
+      bad += 1;
+  return bad ? -1 : 0;
+}
+
 extern "C" {
 
 int mhd_oracle_threads(void) {
@@ -692,51 +803,12 @@ int mhd_oracle_cfl_many(int32_t npatch, const int32_t* dims, int32_t g, const do
 
 int mhd_oracle_fill_guards(int32_t npatch, const int32_t* dims, int32_t g, double* U,
                            const int32_t* nbr) {
-  if (npatch < 0 || !U || !nbr) return -1;
-  std::vector<Geom> Gs(npatch);
-  std::vector<long> base(npatch + 1, 0);
-  for (int p = 0; p < npatch; ++p) {
-    if (!Gs[p].init(dims + 3 * p, g)) return -1;
-    base[p + 1] = base[p] + 8 * Gs[p].Nc;
-  }
-  int bad = 0;
-  for (int p = 0; p < npatch && !bad; ++p) {
-    const Geom& G = Gs[p];
-    for (int k = 0; k < G.N[2]; ++k)
-      for (int j = 0; j < G.N[1]; ++j)
-        for (int i = 0; i < G.N[0]; ++i) {
-          int idx[3] = {i, j, k}, o[3];
-          bool guard = false;
-          for (int d = 0; d < 3; ++d) {
-            o[d] = 0;
-            if (!G.act[d]) continue;
-            if (idx[d] < g) o[d] = -1;
-            else if (idx[d] >= g + G.n[d]) o[d] = +1;
-            if (o[d]) guard = true;
-          }
-          if (!guard) continue;
-          // directions whose face neighbour is the domain boundary: zero-gradient copy
-          for (int d = 0; d < 3; ++d) {
-            if (!o[d]) continue;
-            int fo[3] = {0, 0, 0};
-            fo[d] = o[d];
-            if (nbr[27 * p + (fo[0] + 1) + 3 * (fo[1] + 1) + 9 * (fo[2] + 1)] < 0) {
-              idx[d] = std::min(std::max(idx[d], g), g + G.n[d] - 1);
-              o[d] = 0;
-            }
-          }
-          int src = p;
-          if (o[0] || o[1] || o[2]) src = nbr[27 * p + (o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1)];
-          if (src < 0 || src >= npatch) { bad = 1; break; }
-          const Geom& H = Gs[src];
-          if (H.n[0] != G.n[0] || H.n[1] != G.n[1] || H.n[2] != G.n[2]) { bad = 1; break; }
-          const long cs = (idx[0] - o[0] * G.n[0]) + H.st[1] * (idx[1] - o[1] * G.n[1]) +
-                          H.st[2] * (idx[2] - o[2] * G.n[2]);
-          const long cd = (long)i + G.st[1] * j + G.st[2] * k;
-          for (int m = 0; m < 8; ++m) U[base[p] + m * G.Nc + cd] = U[base[src] + m * H.Nc + cs];
-        }
-  }
-  return bad ? -1 : 0;
+  return fill_guards_t(npatch, dims, g, U, nbr);
+}
+
+int mhd_oracle_fill_guards_ext(int32_t npatch, const int32_t* dims, int32_t g, long double* U,
+                               const int32_t* nbr) {
+  return fill_guards_t(npatch, dims, g, U, nbr);
 }
 
 int mhd_oracle_step_jvp(const int32_t n[3], int32_t g, const double* U_in, const double* dU_in,
@@ -766,6 +838,26 @@ int mhd_oracle_step_jvp_many(int32_t npatch, const int32_t* dims, int32_t g, con
                             dU_out + base[p], dt[p], dx + 3 * p, prm))
       bad += 1;
   return bad ? -1 : 0;
+}
+
+int mhd_oracle_step_sig(const int32_t n[3], int32_t g, const double* U_in, double* U_out,
+                        double dt, const double dx[3], const mhd_oracle_params* prm,
+                        uint64_t* sig) {
+  if (!sig) return -1;
+  return step_traced(n, g, U_in, U_out, dt, dx, prm, sig);
+}
+
+int mhd_oracle_step_sig_many(int32_t npatch, const int32_t* dims, int32_t g, const double* U_in,
+                             double* U_out, const double* dt, const double* dx,
+                             const mhd_oracle_params* prm, uint64_t* sig) {
+  if (!sig) return -1;
+  return step_traced_many(npatch, dims, g, U_in, U_out, dt, dx, prm, sig);
+}
+
+int mhd_oracle_step_ext_many(int32_t npatch, const int32_t* dims, int32_t g,
+                             const long double* U_in, long double* U_out, const double* dt,
+                             const double* dx, const mhd_oracle_params* prm, uint64_t* sig) {
+  return step_traced_many(npatch, dims, g, U_in, U_out, dt, dx, prm, sig);
 }
 
 int mhd_oracle_count_ops(const int32_t n[3], int32_t g, const double* U_in, double dt,

@@ -68,6 +68,28 @@ int mhd_oracle_step_jvp_many(int32_t npatch, const int32_t* dims, int32_t g,
                              double* dU_out, const double* dt, const double* dx,
                              const mhd_oracle_params* prm);
 
+/* Same result as mhd_oracle_step (bitwise), plus a branch signature: a 64-bit hash of
+ * the outcome of every comparison the update makes (limiter cases, min/max/|.| choices,
+ * HLLD regions and degeneracy switch, floors), in program order.  Two inputs with equal
+ * signatures took the same branch of the piecewise-smooth update (up to hash collisions).
+ * sig is uint64_t[1], resp. uint64_t[P] for the multi-patch form. */
+int mhd_oracle_step_sig(const int32_t n[3], int32_t g, const double* U_in, double* U_out,
+                        double dt, const double dx[3], const mhd_oracle_params* prm,
+                        uint64_t* sig);
+int mhd_oracle_step_sig_many(int32_t npatch, const int32_t* dims, int32_t g,
+                             const double* U_in, double* U_out, const double* dt,
+                             const double* dx, const mhd_oracle_params* prm, uint64_t* sig);
+
+/* The update and the guard fill in x87 extended precision (long double, 64-bit
+ * significand), with the branch signature as above (sig may be NULL).  The scheme,
+ * parameters, dt and dx are the FP64 ones; only the rounding of the state arithmetic is
+ * finer.  For finite differences whose step must be smaller than FP64 round-off allows. */
+int mhd_oracle_step_ext_many(int32_t npatch, const int32_t* dims, int32_t g,
+                             const long double* U_in, long double* U_out, const double* dt,
+                             const double* dx, const mhd_oracle_params* prm, uint64_t* sig);
+int mhd_oracle_fill_guards_ext(int32_t npatch, const int32_t* dims, int32_t g, long double* U,
+                               const int32_t* nbr);
+
 /* Arithmetic performed by one patch update, counted by class:
  * counts[0] add/sub, [1] mul, [2] div, [3] sqrt, [4] compare/min/max/abs. */
 int mhd_oracle_count_ops(const int32_t n[3], int32_t g, const double* U_in, double dt,
