@@ -11,7 +11,11 @@ Prints one JSON line: cell-updates/s for FP64 (headline) with the FP32 result, t
 per-kernel HIP-event timings, the roofline of the update and the oracle timed on the
 host cores.
 
+Also measured (FP32, "batched vs per-bunch"): an uneven bunch of 3600 patches of four
+sizes, each at its own CFL step, as one HIP-graph launch vs per-bunch vs per-patch launches.
+
   python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-fp32] [--no-cpu-baseline]
+                  [--no-batched] [--batched-steps 10]
 """
 import argparse
 import json
@@ -34,7 +38,7 @@ def algorithmic_bytes_per_cell(n, g, s):
     return 8.0 * s * (((n + 2 * g) / n) ** 3 + 1.0)
 
 
-def run_precision(w, precision, steps, warmup, flops_per_cell):
+def run_precision(w, precision, steps, warmup, flops_per_cell, tile=None):
     import numpy as np
     import torch
 
@@ -54,6 +58,17 @@ def run_precision(w, precision, steps, warmup, flops_per_cell):
         B.cfl(a, dx, dt, global_min=True)
         B.update(a, b, dt, dx)
 
+    # launch configuration: the autotuner times every tile shape (with and without the XCD
+    # remap) on this state and keeps the fastest
+    B.fill_guards(Ua, nbr)
+    B.cfl(Ua, dx, dt, global_min=True)
+    cfgs = B.tile_configs()
+    if tile is None:
+        best, tune_ms = B.autotune(Ua, Ub, dt, dx, reps=2)
+        log(f"[bench] autotune: " + ", ".join(f"{c}:{m:.2f}ms" for c, m in zip(cfgs, tune_ms)))
+    else:                         # fixed configuration (profiling runs)
+        best, tune_ms = tile, [float("nan")] * len(cfgs)
+        B.set_tile(tile)
     for _ in range(warmup):
         step(Ua, Ub)
         Ua, Ub = Ub, Ua
@@ -96,11 +111,151 @@ def run_precision(w, precision, steps, warmup, flops_per_cell):
         "bytes_per_cell": bpc,
         "update_tflops": flops_per_cell * cells / (upd_ms * 1e-3) / 1e12,
         "update_hbm_gbs": bpc * cells / (upd_ms * 1e-3) / 1e9,
+        "tile": {"chosen": list(cfgs[best]),
+                 "tuned_ms": {str(list(c)): (None if m != m else round(m, 3))
+                              for c, m in zip(cfgs, tune_ms)}},
         "state_host": Ua,
         "dt": dt,
         "bunch": B,
     }
     return res
+
+
+def run_batched(steps, steps_per_patch):
+    """Uneven bunch (2000 x 16^3, 1000 x 24^3, 500 x 32^3, 100 x 48^3, FP32, frozen
+    guards, each patch at its own CFL step): (A) the whole bunch in one launch set per
+    step, all steps in one HIP graph launch; (B) plain launches per same-size bunch of at
+    most 300 patches; (C) launches per patch.  Same kernels and per-patch dt, so the three
+    give identical bits; reported as cell-updates/s."""
+    import numpy as np
+    import torch
+
+    from paper_2508_09568_amd import workloads as W
+    from paper_2508_09568_amd.binding import Bunch
+
+    t0 = time.perf_counter()
+    w = W.uneven(device="cuda", dtype=torch.float32)
+    L = w.layout
+    log(f"[bench] uneven bunch: {L.P} patches, {L.interior_cells} cells, generated in "
+        f"{time.perf_counter() - t0:.1f} s")
+    cells = int(L.interior_cells)
+    U0 = w.U
+    dx = torch.as_tensor(w.dx).cuda()
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    # (A) one bunch, graph of `steps` steps
+    B = Bunch(L.dims, g=L.g, precision=4, gamma=w.gamma, cfl=w.cfl)
+    Ua, Ub = U0.clone(), U0.clone()        # frozen guards: both buffers carry them
+    dt = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    B.cfl(Ua, dx, dt)
+    best, tune_ms = B.autotune(Ua, Ub, dt, dx, reps=2)
+    B.graph_capture(steps, Ua, Ub, dt, dx, nbr=None, dt_mode=1)
+    Ua.copy_(U0)
+    B.graph_launch()                       # warm-up replay
+    Ua.copy_(U0)
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record()
+    B.graph_launch()
+    b.record()
+    torch.cuda.synchronize()
+    ms_a = a.elapsed_time(b)
+    if B.check() != 0:
+        raise RuntimeError("device status after the batched run")
+    res_a = (Ua if steps % 2 == 0 else Ub).clone()
+    cfg = B.tile_configs()[best]
+    del B, Ua, Ub
+    torch.cuda.empty_cache()
+    log(f"[bench] (A) batched graph: {ms_a / steps:.2f} ms/step, tile {cfg}")
+
+    def sub_bunches(groups):
+        subs = []
+        for idx in groups:
+            idx = np.asarray(idx)
+            Bs = Bunch(L.dims[idx], g=L.g, precision=4, gamma=w.gamma, cfl=w.cfl)
+            Bs.set_tile(best if best < len(Bs.tile_configs()) else 0)
+            seg = [U0[int(L.base[p]):int(L.base[p + 1])] for p in idx]
+            ua = torch.cat(seg)
+            subs.append((idx, Bs, ua, ua.clone(), dx[torch.as_tensor(idx).cuda()].contiguous(),
+                         torch.zeros(len(idx), dtype=torch.float64, device="cuda")))
+        return subs
+
+    def run_subs(subs, nst):
+        cur = [(s[2], s[3]) for s in subs]
+        for _ in range(nst):
+            nxt = []
+            for (idx, Bs, _, _, dxs, dts), (x, y) in zip(subs, cur):
+                Bs.cfl(x, dxs, dts)
+                Bs.update(x, y, dts, dxs)
+                nxt.append((y, x))
+            cur = nxt
+        return cur
+
+    def compare(subs, cur, ref):
+        bad = 0.0
+        for (idx, Bs, *_), (x, _) in zip(subs, cur):
+            off = 0
+            for p in idx[:3]:
+                n = int(L.base[p + 1] - L.base[p])
+                d = (x[off:off + n] - ref[int(L.base[p]):int(L.base[p + 1])]).abs().max().item()
+                bad = max(bad, d)
+                off += n
+        return bad
+
+    sizes = L.dims[:, 0]
+    groups = []
+    for n in sorted(set(int(v) for v in sizes)):
+        ids = np.nonzero(sizes == n)[0]
+        groups += [ids[i:i + 300] for i in range(0, len(ids), 300)]
+    subs = sub_bunches(groups)
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record()
+    cur = run_subs(subs, steps)
+    b.record()
+    torch.cuda.synchronize()
+    ms_b = a.elapsed_time(b)
+    diff_b = compare(subs, cur, res_a)
+    log(f"[bench] (B) per-bunch ({len(subs)} bunches): {ms_b / steps:.2f} ms/step, "
+        f"max |B - A| on sampled patches {diff_b:.3e}")
+    del subs, cur
+    torch.cuda.empty_cache()
+
+    subs = sub_bunches([[p] for p in range(L.P)])
+    torch.cuda.synchronize()
+    run_subs(subs, 1)                      # warm-up (first launches of each handle)
+    for s_ in subs:
+        s_[2].copy_(U0[int(L.base[s_[0][0]]):int(L.base[s_[0][0] + 1])])
+        s_[3].copy_(s_[2])
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record()
+    run_subs(subs, steps_per_patch)
+    b.record()
+    torch.cuda.synchronize()
+    ms_c = a.elapsed_time(b)
+    log(f"[bench] (C) per-patch ({len(subs)} launches sets/step): "
+        f"{ms_c / steps_per_patch:.2f} ms/step")
+    del subs
+    torch.cuda.empty_cache()
+    return {
+        "workload": "uneven bunch: 2000 x 16^3 + 1000 x 24^3 + 500 x 32^3 + 100 x 48^3 "
+                    "patches (guard 3, frozen guards), turbulence field sampled per patch, "
+                    "each patch at its own CFL step; FP32",
+        "cell_updates_per_step": cells,
+        "steps": steps,
+        "batched_graph": {"value": cells * steps / (ms_a * 1e-3), "ms_per_step": ms_a / steps,
+                          "launch": "one HIP graph launch for all steps (CFL + update "
+                                    "kernels of the whole bunch per step)",
+                          "tile": list(cfg)},
+        "per_bunch": {"value": cells * steps / (ms_b * 1e-3), "ms_per_step": ms_b / steps,
+                      "bunches": len(groups), "launch": "same-size bunches of <= 300 patches",
+                      "max_abs_diff_vs_batched": diff_b},
+        "per_patch": {"value": cells * steps_per_patch / (ms_c * 1e-3),
+                      "ms_per_step": ms_c / steps_per_patch, "steps": steps_per_patch},
+        "speedup_vs_per_bunch": ms_b / ms_a,
+        "speedup_vs_per_patch": (ms_c / steps_per_patch) / (ms_a / steps),
+    }
 
 
 def cpu_baseline(w, state_gpu, dt_gpu, npatch):
@@ -145,7 +300,23 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-patches", type=int, default=256)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--tile", type=int, default=None,
+                    help="use this launch configuration instead of autotuning")
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run 5 plain device-to-device copies of this many bytes (HBM "
+                         "counter calibration under rocprofv3 --pmc) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the update has no multi-GPU path in this "
               "build (patches would shard by contiguous blocks with a guard exchange per "
@@ -171,7 +342,7 @@ def main():
     flops = float(ops[:4].sum())
 
     log(f"[bench] FP64: warmup {args.warmup}, timed {args.steps} steps")
-    r64 = run_precision(w, 8, args.steps, args.warmup, flops)
+    r64 = run_precision(w, 8, args.steps, args.warmup, flops, args.tile)
     log(f"[bench] FP64 {r64['value']:.4e} cell-updates/s, {r64['ms_per_step']:.2f} ms/step")
     cpu = None
     if not args.no_cpu_baseline:
@@ -184,10 +355,17 @@ def main():
     r32 = None
     if not args.no_fp32:
         log(f"[bench] FP32: warmup {args.warmup}, timed {args.steps} steps")
-        r32 = run_precision(w, 4, args.steps, args.warmup, flops)
+        r32 = run_precision(w, 4, args.steps, args.warmup, flops, args.tile)
         for k in ("state_host", "dt", "bunch"):
             r32.pop(k)
         log(f"[bench] FP32 {r32['value']:.4e} cell-updates/s, {r32['ms_per_step']:.2f} ms/step")
+
+    batched = None
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        batched = run_batched(args.batched_steps, 2)
+        log(f"[bench] batched vs per-bunch {batched['speedup_vs_per_bunch']:.2f}x, "
+            f"vs per-patch {batched['speedup_vs_per_patch']:.2f}x")
 
     peak = PEAK_VALU_TFLOPS[8]
     out = {
@@ -227,13 +405,16 @@ def main():
             "bytes_per_cell": r64["bytes_per_cell"],
         },
         "kernels_ms": {k: v["avg_ms"] for k, v in r64["kernels"].items()},
+        "tile": r64["tile"],
         "fp32": None if r32 is None else {
             "value": r32["value"], "ms_per_step": r32["ms_per_step"],
             "update_ms_per_launch": r32["update_ms_per_launch"],
             "alu_frac": r32["update_tflops"] / PEAK_VALU_TFLOPS[4],
             "hbm_frac": r32["update_hbm_gbs"] / PEAK_HBM_GBS,
             "kernels_ms": {k: v["avg_ms"] for k, v in r32["kernels"].items()},
+            "tile": r32["tile"],
         },
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

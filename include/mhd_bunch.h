@@ -116,6 +116,71 @@ mhd_status mhd_bunch_cfl(mhd_bunch* h, const void* U_dev, const double* dx_dev,
 mhd_status mhd_bunch_update(mhd_bunch* h, const void* U_in, void* U_out, const double* dt_dev,
                             const double* dx_dev, hipStream_t stream);
 
+/* ---- adjoint of one update (reverse mode at fixed dt) ----
+ * The step map is U^{n+1}(owned) = update(fill_guards(U^n)).  mhd_bunch_adjoint returns
+ * lam_in = (d U^{n+1} / d U^n)^T lam_out: lam_out holds dL/dU^{n+1} on owned cells and faces
+ * (its guard entries are ignored); lam_in receives dL/dU^n on owned entries and zero in the
+ * guards, the guard copies' adjoints having been added to their owners.  U_in must be U^n
+ * with guards filled (the update's input).  Every adjoint element is a deterministic gather
+ * over the forward items that read the corresponding input, differentiated in dual numbers.
+ *
+ * nbr_host: the host copy of the neighbour table used by mhd_bunch_fill_guards ([P][27]),
+ * or NULL when guards are frozen inputs (then guard entries of lam_in are their own
+ * adjoints and nothing is folded).  mhd_bunch_adjoint_workspace_bytes builds the
+ * owner -> guard-copies map on the host and returns the device bytes that
+ * mhd_bunch_adjoint_bind needs (caller-owned, 256-byte aligned). */
+int64_t mhd_bunch_adjoint_workspace_bytes(mhd_bunch* h, const int32_t* nbr_host);
+mhd_status mhd_bunch_adjoint_bind(mhd_bunch* h, const int32_t* nbr_host, void* adjoint_workspace_dev,
+                                  hipStream_t stream);
+mhd_status mhd_bunch_adjoint(mhd_bunch* h, const void* U_in, const void* lam_out, void* lam_in,
+                             const double* dt_dev, const double* dx_dev, hipStream_t stream);
+
+/* ---- launch configuration and autotuning ----
+ * The solver kernel works on 3D tiles of a patch's interior (every face flux and edge EMF
+ * of the tile into shared memory, then the update).  A bunch has 3*S launch
+ * configurations: S tile shapes for its dimensionality, each in three launch modes:
+ *   0 plain grid (one work-group per tile or block of 256 items);
+ *   1 the same with the XCD remap (work-groups, handed round-robin to the 8 XCDs, take
+ *     contiguous ranges of the tile and block tables, so neighbouring tiles share an L2);
+ *   2 persistent grids sized to the device (work-groups loop over the tables), remapped.
+ * Configuration 0 is the default.  mhd_bunch_tile_get fills
+ * cfg = {tile x, tile y, tile z, mode}.  Every configuration gives the same bits. */
+int32_t mhd_bunch_tile_count(const mhd_bunch* h);
+int32_t mhd_bunch_tile_current(const mhd_bunch* h);
+mhd_status mhd_bunch_tile_get(const mhd_bunch* h, int32_t index, int32_t cfg[4]);
+mhd_status mhd_bunch_tile_set(mhd_bunch* h, int32_t index);
+
+/* Predictor stages: 0 = three kernels (primitives, edge EMFs at time n, predictor) through
+ * the workspace scratch; 1 = one tiled kernel that keeps primitives and EMFs of a tile (plus
+ * one cell around it) in shared memory.  Same values either way.  Default 0. */
+mhd_status mhd_bunch_set_predictor(mhd_bunch* h, int32_t fused);
+int32_t mhd_bunch_predictor(const mhd_bunch* h);
+
+/* Times every configuration on the caller's data (one warm-up and `reps` timed updates of
+ * U_in -> U_out each, HIP events on `stream`) and keeps the fastest; then times both
+ * predictor forms with that configuration and keeps the faster.  Synchronises `stream`;
+ * overwrites U_out.  best (may be NULL) receives the chosen index, ms (may be NULL, else
+ * float[mhd_bunch_tile_count]) the mean update time of each configuration. */
+mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* U_in, void* U_out, const double* dt_dev,
+                              const double* dx_dev, int32_t reps, hipStream_t stream,
+                              int32_t* best, float* ms);
+
+/* ---- batched multi-step runs in one HIP graph ----
+ * Captures nsteps steps into a HIP graph owned by the handle (replacing any earlier one):
+ * step k advances U_a -> U_b for even k and U_b -> U_a for odd k, with
+ *   nbr_dev != NULL: the guards of the step's input filled first (as mhd_bunch_fill_guards);
+ *                    NULL: guards are frozen inputs;
+ *   dt_mode 0: dt_dev used as given; 1: dt_dev[p] = the patch's own CFL step of the step's
+ *              input (local time stepping, each patch at its own dt); 2: global minimum.
+ * Every launch of every step uses the launch configuration current at capture time.
+ * Buffers are bound by address: they must stay allocated while the graph is launched.
+ * Capture uses a private stream; nothing runs until mhd_bunch_graph_launch enqueues the
+ * whole run on `stream`. */
+mhd_status mhd_bunch_graph_capture(mhd_bunch* h, int32_t nsteps, void* U_a, void* U_b,
+                                   double* dt_dev, const double* dx_dev, const int32_t* nbr_dev,
+                                   int32_t dt_mode, hipStream_t stream);
+mhd_status mhd_bunch_graph_launch(mhd_bunch* h, hipStream_t stream);
+
 /* Synchronises `stream`, then returns MHD_ENONPHYS if any kernel since the last check
  * met a non-physical state (and clears the flag), else MHD_OK. */
 mhd_status mhd_bunch_check(mhd_bunch* h, hipStream_t stream);

@@ -82,6 +82,19 @@ _SIGS = {
     "mhd_bunch_profile_read": (C.c_int, [_h, C.c_int32, _dp, C.POINTER(C.c_int64)]),
     "mhd_status_string": (C.c_char_p, [C.c_int]),
     "mhd_bunch_last_error": (C.c_char_p, [_h]),
+    "mhd_bunch_adjoint_workspace_bytes": (C.c_int64, [_h, _v]),
+    "mhd_bunch_adjoint_bind": (C.c_int, [_h, _v, _v, _st]),
+    "mhd_bunch_adjoint": (C.c_int, [_h, _v, _v, _v, _v, _v, _st]),
+    "mhd_bunch_tile_count": (C.c_int32, [_h]),
+    "mhd_bunch_tile_current": (C.c_int32, [_h]),
+    "mhd_bunch_tile_get": (C.c_int, [_h, C.c_int32, _ip]),
+    "mhd_bunch_tile_set": (C.c_int, [_h, C.c_int32]),
+    "mhd_bunch_autotune": (C.c_int, [_h, _v, _v, _v, _v, C.c_int32, _st, _ip,
+                                     C.POINTER(C.c_float)]),
+    "mhd_bunch_graph_capture": (C.c_int, [_h, C.c_int32, _v, _v, _v, _v, _v, C.c_int32, _st]),
+    "mhd_bunch_graph_launch": (C.c_int, [_h, _st]),
+    "mhd_bunch_set_predictor": (C.c_int, [_h, C.c_int32]),
+    "mhd_bunch_predictor": (C.c_int32, [_h]),
 }
 
 KERNELS = {"prim": 0, "edge_emf_n": 1, "predict": 2, "solve": 3, "cfl": 4, "guards": 5}
@@ -191,6 +204,28 @@ class Bunch:
     def check(self, stream=None):
         return mhd_bunch_check(self._h, _stream(stream))
 
+    def adjoint_bind(self, nbr_host=None, stream=None):
+        """Allocate and bind the adjoint workspace.  nbr_host: (P, 27) int32 host neighbour
+        table of the guard fill (guard adjoints fold onto owners), or None for frozen
+        guards."""
+        import numpy as np
+        import torch
+        self._nbr_host = None if nbr_host is None else np.ascontiguousarray(nbr_host, dtype=np.int32)
+        ptr = None if self._nbr_host is None else self._nbr_host.ctypes.data_as(C.c_void_p)
+        nb = int(mhd_bunch_adjoint_workspace_bytes(self._h, ptr))
+        if nb < 0:
+            raise MhdError(MHD_EINVAL, "mhd_bunch_adjoint_workspace_bytes")
+        self.adjoint_workspace = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        _ok(mhd_bunch_adjoint_bind(self._h, ptr, _ptr(self.adjoint_workspace), _stream(stream)),
+            "mhd_bunch_adjoint_bind", self._h)
+
+    def adjoint(self, U_in, lam_out, lam_in, dt, dx, stream=None):
+        """lam_in = (dU_out/dU_in)^T lam_out for one update at fixed dt (U_in guards filled)."""
+        for t in (U_in, lam_out, lam_in):
+            self._check_state(t)
+        _ok(mhd_bunch_adjoint(self._h, _ptr(U_in), _ptr(lam_out), _ptr(lam_in), _ptr(dt), _ptr(dx),
+                              _stream(stream)), "mhd_bunch_adjoint", self._h)
+
     def profile(self, enable=True):
         _ok(mhd_bunch_profile(self._h, int(bool(enable))), "mhd_bunch_profile")
 
@@ -204,3 +239,52 @@ class Bunch:
                 "mhd_bunch_profile_read")
             out[name] = (ms.value, n.value)
         return out
+
+    # ---- launch configurations, autotuning, graph-captured runs
+    def tile_configs(self):
+        """[(tile_x, tile_y, tile_z, mode)] of every launch configuration (mode 0 plain grid,
+        1 XCD remap, 2 persistent grid + remap)."""
+        out = []
+        for i in range(int(mhd_bunch_tile_count(self._h))):
+            cfg = (C.c_int32 * 4)()
+            _ok(mhd_bunch_tile_get(self._h, i, cfg), "mhd_bunch_tile_get")
+            out.append(tuple(int(v) for v in cfg))
+        return out
+
+    def tile(self):
+        return int(mhd_bunch_tile_current(self._h))
+
+    def set_tile(self, index):
+        _ok(mhd_bunch_tile_set(self._h, int(index)), "mhd_bunch_tile_set")
+
+    def set_predictor(self, fused):
+        _ok(mhd_bunch_set_predictor(self._h, int(bool(fused))), "mhd_bunch_set_predictor")
+
+    def predictor(self):
+        return int(mhd_bunch_predictor(self._h))
+
+    def autotune(self, U_in, U_out, dt, dx, reps=3, stream=None):
+        """Time every launch configuration on these buffers and keep the fastest; returns
+        (chosen index, [mean ms per update of each configuration])."""
+        self._check_state(U_in)
+        self._check_state(U_out)
+        n = int(mhd_bunch_tile_count(self._h))
+        ms = (C.c_float * n)()
+        best = C.c_int32()
+        _ok(mhd_bunch_autotune(self._h, _ptr(U_in), _ptr(U_out), _ptr(dt), _ptr(dx), int(reps),
+                               _stream(stream), C.byref(best), ms), "mhd_bunch_autotune", self._h)
+        return int(best.value), [float(v) for v in ms]
+
+    def graph_capture(self, nsteps, U_a, U_b, dt, dx, nbr=None, dt_mode=0, stream=None):
+        """Capture nsteps ping-pong steps (U_a -> U_b -> U_a ...) in one HIP graph;
+        dt_mode 0 = dt as given, 1 = per-patch own CFL step, 2 = global minimum;
+        nbr = device neighbour table to fill guards before each step, or None (frozen)."""
+        self._check_state(U_a)
+        self._check_state(U_b)
+        self._graph_refs = (U_a, U_b, dt, dx, nbr)   # keep the bound buffers alive
+        _ok(mhd_bunch_graph_capture(self._h, int(nsteps), _ptr(U_a), _ptr(U_b), _ptr(dt), _ptr(dx),
+                                    None if nbr is None else _ptr(nbr), int(dt_mode),
+                                    _stream(stream)), "mhd_bunch_graph_capture", self._h)
+
+    def graph_launch(self, stream=None):
+        _ok(mhd_bunch_graph_launch(self._h, _stream(stream)), "mhd_bunch_graph_launch", self._h)

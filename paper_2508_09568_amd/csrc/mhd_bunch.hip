@@ -32,6 +32,24 @@ struct DevX {
   __device__ void sync() const { __syncthreads(); }
 };
 
+// Work-groups are handed to the 8 XCDs round-robin (block b runs on XCD b % 8), and each
+// XCD has its own L2.  With remap on, block b takes logical block remap_xcd(b, nb), which
+// gives every XCD one contiguous range of the block table: neighbouring tiles of a patch,
+// whose halos overlap, then share one L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int remap_xcd(int b, int nb) {
+  const int per = nb / NXCD, rem = nb % NXCD, x = b % NXCD, i = b / NXCD;
+  return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+// Kernels over a block (or tile) table of nb entries loop over virtual blocks
+// vb = blockIdx.x, blockIdx.x + gridDim.x, ...: one virtual block per work-group when the
+// grid is nb (plain launch), several when the grid is a persistent one sized to the machine.
+// A persistent grid is a multiple of NXCD, so every virtual block of a work-group runs on
+// that work-group's XCD and remap_xcd keeps its meaning.
+__device__ __forceinline__ int logical_block(int vb, int nb, int remap) {
+  return remap ? remap_xcd(vb, nb) : vb;
+}
+
 __device__ __forceinline__ bool decode(const PatchDev& P, int kind, int g, int first, int& i, int& j,
                                        int& k) {
   int lo[3], sz[3];
@@ -48,23 +66,28 @@ template <typename T>
 __global__ __launch_bounds__(BLK) void k_prim(const PatchDev* __restrict__ pt,
                                               const BoxBlock* __restrict__ blk,
                                               const T* __restrict__ U, T* __restrict__ S,
-                                              Consts<T> c, int g, int* status) {
-  const BoxBlock b = blk[blockIdx.x];
-  const PatchDev P = pt[b.patch];
-  int i, j, k;
-  if (!decode(P, BOX_PRIM, g, b.first, i, j, k)) return;
-  if (prim_item(P, cell_of(P, i, j, k), U, S, c)) atomicOr(status, 1);
+                                              Consts<T> c, int g, int* status, int nb, int remap) {
+  for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
+    const BoxBlock b = blk[logical_block(vb, nb, remap)];
+    const PatchDev& P = pt[b.patch];
+    int i, j, k;
+    if (!decode(P, BOX_PRIM, g, b.first, i, j, k)) continue;
+    if (prim_item(P, cell_of(P, i, j, k), U, S, c)) atomicOr(status, 1);
+  }
 }
 
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_en(const PatchDev* __restrict__ pt,
                                             const BoxBlock* __restrict__ blk,
-                                            const T* __restrict__ U, T* __restrict__ S, int g) {
-  const BoxBlock b = blk[blockIdx.x];
-  const PatchDev P = pt[b.patch];
-  int i, j, k;
-  if (!decode(P, BOX_EN, g, b.first, i, j, k)) return;
-  en_item(P, cell_of(P, i, j, k), U, S);
+                                            const T* __restrict__ U, T* __restrict__ S, int g,
+                                            int nb, int remap) {
+  for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
+    const BoxBlock b = blk[logical_block(vb, nb, remap)];
+    const PatchDev& P = pt[b.patch];
+    int i, j, k;
+    if (!decode(P, BOX_EN, g, b.first, i, j, k)) continue;
+    en_item(P, cell_of(P, i, j, k), U, S);
+  }
 }
 
 template <typename T>
@@ -72,24 +95,47 @@ __global__ __launch_bounds__(BLK) void k_pred(const PatchDev* __restrict__ pt,
                                               const BoxBlock* __restrict__ blk,
                                               const T* __restrict__ U, T* __restrict__ S,
                                               const double* __restrict__ dt,
-                                              const double* __restrict__ dx, Consts<T> c, int g) {
-  const BoxBlock b = blk[blockIdx.x];
-  const PatchDev P = pt[b.patch];
-  int i, j, k;
-  if (!decode(P, BOX_PRED, g, b.first, i, j, k)) return;
-  pred_item(P, g, i, j, k, U, S, S, dt[b.patch], dx + 3 * b.patch, c);
+                                              const double* __restrict__ dx, Consts<T> c, int g,
+                                              int nb, int remap) {
+  for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
+    const BoxBlock b = blk[logical_block(vb, nb, remap)];
+    const PatchDev& P = pt[b.patch];
+    int i, j, k;
+    if (!decode(P, BOX_PRED, g, b.first, i, j, k)) continue;
+    pred_item(P, g, i, j, k, U, S, S, dt[b.patch], dx + 3 * b.patch, c);
+  }
 }
 
 template <typename T, int TX, int TY, int TZ>
 __global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS)) void k_solve(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, const T* __restrict__ Uin,
     T* __restrict__ Uout, const T* __restrict__ S, const double* __restrict__ dt,
-    const double* __restrict__ dx, Consts<T> c, int g) {
+    const double* __restrict__ dx, Consts<T> c, int g, int ntile, int remap) {
   __shared__ T lds[TileShape<TX, TY, TZ>::LDS_ELEMS];
-  const TileDev tl = tiles[blockIdx.x];
-  const PatchDev P = pt[tl.patch];
   DevX ex;
-  solve_tile<T, TX, TY, TZ>(ex, lds, P, g, tl, Uin, Uout, S, dt[tl.patch], dx + 3 * tl.patch, c);
+  for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
+    const TileDev tl = tiles[logical_block(vb, ntile, remap)];
+    const PatchDev& P = pt[tl.patch];
+    solve_tile<T, TX, TY, TZ>(ex, lds, P, g, tl, Uin, Uout, S, dt[tl.patch], dx + 3 * tl.patch, c);
+    ex.sync();  // the next tile reuses the shared memory
+  }
+}
+
+template <typename T, int PX, int PY, int PZ>
+__global__ __launch_bounds__((PredShape<PX, PY, PZ>::THREADS)) void k_predict(
+    const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, const T* __restrict__ U,
+    T* __restrict__ W, const double* __restrict__ dt, const double* __restrict__ dx, Consts<T> c,
+    int g, int* status, int ntile, int remap) {
+  __shared__ T lds[PredShape<PX, PY, PZ>::LDS_ELEMS];
+  DevX ex;
+  int bad = 0;
+  for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
+    const TileDev tl = tiles[logical_block(vb, ntile, remap)];
+    const PatchDev& P = pt[tl.patch];
+    bad |= predict_tile<T, PX, PY, PZ>(ex, lds, P, g, tl, U, W, dt[tl.patch], dx + 3 * tl.patch, c);
+    ex.sync();  // the next tile reuses the shared memory
+  }
+  if (bad) atomicOr(status, 1);
 }
 
 template <typename T>
@@ -98,7 +144,7 @@ __global__ __launch_bounds__(BLK) void k_cfl(const PatchDev* __restrict__ pt,
                                              const T* __restrict__ U, const double* __restrict__ dx,
                                              Consts<T> c, int g, unsigned long long* smax) {
   const BoxBlock b = blk[blockIdx.x];
-  const PatchDev P = pt[b.patch];
+  const PatchDev& P = pt[b.patch];
   int i, j, k;
   double s = 0.0;
   if (decode(P, BOX_INTERIOR, g, b.first, i, j, k))
@@ -144,13 +190,144 @@ __global__ __launch_bounds__(BLK) void k_guards(const PatchDev* __restrict__ pt,
                                                 const int32_t* __restrict__ nbr, int g, int np,
                                                 int* status) {
   const BoxBlock b = blk[blockIdx.x];
-  const PatchDev P = pt[b.patch];
+  const PatchDev& P = pt[b.patch];
   int i, j, k;
   if (!decode(P, BOX_ALL, g, b.first, i, j, k)) return;
   if (guard_item(pt, b.patch, g, i, j, k, U, nbr, np)) atomicOr(status, 2);
 }
 
+// ------------------------------------------------------------------- adjoint kernels
+// grid.x: block table of the item box, grid.y: component
+
+__device__ __forceinline__ bool decode3(const PatchDev& P, int kind, int g, int first, int x[3]) {
+  return decode(P, kind, g, first, x[0], x[1], x[2]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_adj_w(const PatchDev* __restrict__ pt,
+                                               const BoxBlock* __restrict__ blk, const T* __restrict__ S,
+                                               T* __restrict__ LS, const T* __restrict__ lam,
+                                               const double* __restrict__ dt,
+                                               const double* __restrict__ dx, Consts<T> c, int g,
+                                              int remap) {
+  const BoxBlock b = blk[logical_block(blockIdx.x, gridDim.x, remap)];
+  const PatchDev& P = pt[b.patch];
+  int x[3];
+  if (!decode3(P, BOX_PRED, g, b.first, x)) return;
+  const int v = blockIdx.y;
+  LS[P.wbase + (int64_t)v * P.Nwc + wcell_of(P, g, x[0], x[1], x[2])] =
+      adj_w_item(P, g, x, v, S, lam, dt[b.patch], dx + 3 * b.patch, c);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_adj_e(const PatchDev* __restrict__ pt,
+                                               const BoxBlock* __restrict__ blk, const T* __restrict__ U,
+                                               const T* __restrict__ S, T* __restrict__ LS,
+                                               const double* __restrict__ dt,
+                                               const double* __restrict__ dx, Consts<T> c, int g,
+                                              int remap) {
+  const BoxBlock b = blk[logical_block(blockIdx.x, gridDim.x, remap)];
+  const PatchDev& P = pt[b.patch];
+  int x[3];
+  if (!decode3(P, BOX_EN, g, b.first, x)) return;
+  const int k = blockIdx.y;
+  LS[P.sbase + 8 * P.Nc + (int64_t)k * P.Nc + cell_of(P, x[0], x[1], x[2])] =
+      adj_e_item(P, g, x, k, U, S, (const T*)LS, dt[b.patch], dx + 3 * b.patch, c);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_adj_q(const PatchDev* __restrict__ pt,
+                                               const BoxBlock* __restrict__ blk, const T* __restrict__ U,
+                                               const T* __restrict__ S, T* __restrict__ LS,
+                                               const double* __restrict__ dt,
+                                               const double* __restrict__ dx, Consts<T> c, int g,
+                                              int remap) {
+  const BoxBlock b = blk[logical_block(blockIdx.x, gridDim.x, remap)];
+  const PatchDev& P = pt[b.patch];
+  int x[3];
+  if (!decode3(P, BOX_PRIM, g, b.first, x)) return;
+  const int m = blockIdx.y;
+  LS[P.sbase + (int64_t)m * P.Nc + cell_of(P, x[0], x[1], x[2])] =
+      adj_q_item(P, g, x, m, U, S, (const T*)LS, (const T*)LS, dt[b.patch], dx + 3 * b.patch, c);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_adj_u(const PatchDev* __restrict__ pt,
+                                               const BoxBlock* __restrict__ blk, const T* __restrict__ U,
+                                               const T* __restrict__ S, const T* __restrict__ LS,
+                                               const T* __restrict__ lam, T* __restrict__ LU,
+                                               const double* __restrict__ dt,
+                                               const double* __restrict__ dx, Consts<T> c, int g,
+                                              int remap) {
+  const BoxBlock b = blk[logical_block(blockIdx.x, gridDim.x, remap)];
+  const PatchDev& P = pt[b.patch];
+  int x[3];
+  if (!decode3(P, BOX_ALL, g, b.first, x)) return;
+  const int m = blockIdx.y;
+  LU[P.ubase + (int64_t)m * P.Nc + cell_of(P, x[0], x[1], x[2])] =
+      adj_u_item(P, g, x, m, U, S, LS, LS, lam, dt[b.patch], dx + 3 * b.patch, c);
+}
+
+// guard copies are functions of their owners: owners collect the adjoints of their copies
+// (deterministic order of the owner -> copies map built on the host); guards get zero
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_adj_fold(const PatchDev* __restrict__ pt,
+                                                  const BoxBlock* __restrict__ blk,
+                                                  const T* __restrict__ LU, T* __restrict__ lam_in,
+                                                  const int32_t* __restrict__ row,
+                                                  const int32_t* __restrict__ col_patch,
+                                                  const int32_t* __restrict__ col_cell, int g, int fold) {
+  const BoxBlock b = blk[blockIdx.x];
+  const PatchDev& P = pt[b.patch];
+  int x[3];
+  if (!decode3(P, BOX_ALL, g, b.first, x)) return;
+  const int m = blockIdx.y;
+  const int64_t cell = cell_of(P, x[0], x[1], x[2]);
+  const int64_t o = P.ubase + (int64_t)m * P.Nc + cell;
+  if (!fold) {
+    lam_in[o] = LU[o];
+    return;
+  }
+  if (!owned(P, g, x)) {
+    lam_in[o] = T(0);
+    return;
+  }
+  T s = LU[o];
+  const int64_t id = P.ubase / 8 + cell;
+  for (int32_t r = row[id]; r < row[id + 1]; ++r) {
+    const PatchDev& Q = pt[col_patch[r]];
+    s = s + LU[Q.ubase + (int64_t)m * Q.Nc + col_cell[r]];
+  }
+  lam_in[o] = s;
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Solver tile shapes per activity pattern (bit d set = direction d active), the first one
+// the default.  The lists drive both the host-side tables and the kernel instantiations.
+#define MHD_SHAPES_7(F) F(8, 8, 4) F(16, 4, 4) F(8, 4, 8) F(16, 8, 2) F(32, 4, 2) F(8, 8, 2)
+#define MHD_SHAPES_3(F) F(16, 16, 1) F(32, 8, 1) F(64, 4, 1) F(8, 8, 1)
+#define MHD_SHAPES_1(F) F(64, 1, 1) F(128, 1, 1)
+#define MHD_SHAPES_6(F) F(1, 16, 16)
+#define MHD_SHAPES_5(F) F(16, 1, 16)
+#define MHD_SHAPES_2(F) F(1, 64, 1)
+#define MHD_SHAPES_4(F) F(1, 1, 64)
+// fused predictor tile per activity pattern
+#define MHD_PRED_SHAPE(act, F)                \
+  switch (act) {                               \
+    case 7: F(8, 8, 4) break;                  \
+    case 3: F(16, 16, 1) break;                \
+    case 6: F(1, 16, 16) break;                \
+    case 5: F(16, 1, 16) break;                \
+    case 1: F(128, 1, 1) break;                \
+    case 2: F(1, 128, 1) break;                \
+    default: F(1, 1, 128) break;               \
+  }
+constexpr int MAXSHAPE = 6;
+constexpr int NMODE = 3;  // launch modes per tile shape: plain grid, XCD remap, persistent
+struct TileCand {
+  int x, y, z;
+};
 
 }  // namespace
 
@@ -166,18 +343,40 @@ struct mhd_bunch {
   struct Chunk {
     int p0 = 0, p1 = 0;
     int blk0[NBOX] = {0}, nblk[NBOX] = {0};
-    int tile0 = 0, ntile = 0;
+    int tile0[MAXSHAPE] = {0}, ntile[MAXSHAPE] = {0};
+    int ptile0 = 0, nptile = 0;
+    int blk0_all = 0, nblk_all = 0;  // range of the whole-bunch BOX_ALL table
   };
   std::vector<Chunk> chunks;
   std::vector<BoxBlock> blocks[NBOX];
-  std::vector<TileDev> tiles;
-  int TX = 8, TY = 8, TZ = 4;
+  // solver tile shapes for this bunch's dimensionality (mhd_bunch_tile_*), one tile table
+  // per shape; the launch configuration in use is (shape, remap)
+  int nshape = 0, shape = 0, mode = 0;  // mode 0 plain grid, 1 XCD remap, 2 persistent + remap
+  int ncu = 256;                           // compute units of the bound device
+  TileCand shapes[MAXSHAPE];
+  std::vector<TileDev> tiles[MAXSHAPE];
+  // fused predictor (mhd_bunch_set_predictor): tile table over the predictor boxes
+  int fused = 0;
+  int PXs = 8, PYs = 8, PZs = 4;
+  std::vector<TileDev> ptiles;
+  size_t o_ptiles = 0;
   int64_t scratch_elems = 0;
-  size_t o_pt = 0, o_blk[NBOX] = {0}, o_tiles = 0, o_smax = 0, o_status = 0, o_scratch = 0;
+  size_t o_pt = 0, o_blk[NBOX] = {0}, o_tiles[MAXSHAPE] = {0}, o_smax = 0, o_status = 0,
+         o_scratch = 0;
+  // mhd_bunch_graph_capture: instantiated graph of a multi-step run
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
   size_t ws_bytes = 0;
   char* ws = nullptr;
   bool bound = false;
   char last_error[256] = {0};
+  // adjoint workspace: lambda scratch (layout of the forward scratch), lambda of the padded
+  // input state, and the owner -> guard-copies map (CSR over all padded cells)
+  char* aws = nullptr;
+  bool adj_bound = false;
+  bool adj_fold = false;
+  size_t a_ls = 0, a_lu = 0, a_row = 0, a_colp = 0, a_colc = 0, a_bytes = 0;
+  std::vector<int32_t> row, colp, colc;
   // record the first failing HIP call of an API call; returns true on success
   bool hip_ok(hipError_t e, const char* what) {
     if (e == hipSuccess) return true;
@@ -190,7 +389,14 @@ struct mhd_bunch {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<Mark> marks;
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+  }
   ~mhd_bunch() {
+    drop_graph();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
   hipEvent_t ev_get() {
@@ -228,9 +434,18 @@ struct mhd_bunch {
     c.limiter = limiter;
     return c;
   }
+  // persistent grid: at most `per_cu` work-groups per compute unit, a multiple of the XCD
+  // count when it is smaller than the table (see logical_block)
+  int persistent_grid(int nb, int per_cu) const {
+    const int cap = ncu * per_cu;
+    if (nb <= cap) return nb;
+    return std::max(NXCD, cap / NXCD * NXCD);
+  }
+  int stage_grid(int nb) const { return mode == 2 ? persistent_grid(nb, 2048 / BLK) : nb; }
   const PatchDev* d_pt() const { return (const PatchDev*)(ws + o_pt); }
   const BoxBlock* d_blk(int k) const { return (const BoxBlock*)(ws + o_blk[k]); }
-  const TileDev* d_tiles() const { return (const TileDev*)(ws + o_tiles); }
+  const TileDev* d_tiles(int k) const { return (const TileDev*)(ws + o_tiles[k]); }
+  const TileDev* d_ptiles() const { return (const TileDev*)(ws + o_ptiles); }
   unsigned long long* d_smax() const { return (unsigned long long*)(ws + o_smax); }
   int* d_status() const { return (int*)(ws + o_status); }
   void* d_scratch() const { return ws + o_scratch; }
@@ -245,16 +460,53 @@ void add_blocks(std::vector<BoxBlock>& out, const PatchDev& P, int p, int kind, 
   for (int f = 0; f < n; f += BLK) out.push_back(BoxBlock{p, f});
 }
 
-void pick_tile(mhd_bunch* h) {
+void set_shapes(mhd_bunch* h) {
+  h->nshape = 0;
+#define MHD_ADD(X, Y, Z) h->shapes[h->nshape++] = TileCand{X, Y, Z};
   switch (h->act) {
-    case 7: h->TX = 8; h->TY = 8; h->TZ = 4; break;
-    case 3: h->TX = 16; h->TY = 16; h->TZ = 1; break;
-    case 6: h->TX = 1; h->TY = 16; h->TZ = 16; break;
-    case 5: h->TX = 16; h->TY = 1; h->TZ = 16; break;
-    case 1: h->TX = 64; h->TY = 1; h->TZ = 1; break;
-    case 2: h->TX = 1; h->TY = 64; h->TZ = 1; break;
-    default: h->TX = 1; h->TY = 1; h->TZ = 64; break;
+    case 7: MHD_SHAPES_7(MHD_ADD) break;
+    case 3: MHD_SHAPES_3(MHD_ADD) break;
+    case 1: MHD_SHAPES_1(MHD_ADD) break;
+    case 6: MHD_SHAPES_6(MHD_ADD) break;
+    case 5: MHD_SHAPES_5(MHD_ADD) break;
+    case 2: MHD_SHAPES_2(MHD_ADD) break;
+    default: MHD_SHAPES_4(MHD_ADD) break;
   }
+#undef MHD_ADD
+}
+
+template <typename T>
+void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uout, const T* S,
+                  const double* dt, const double* dx, const Consts<T>& c, hipStream_t s) {
+  const int k = h->shape;
+  const TileCand tc = h->shapes[k];
+  const int nt = ch.ntile[k];
+  const TileDev* tl = h->d_tiles(k) + ch.tile0[k];
+#define MHD_TRY(X, Y, Z)                                                                      \
+  if (tc.x == X && tc.y == Y && tc.z == Z) {                                                  \
+    int grid = nt;                                                                            \
+    if (h->mode == 2) {                                                                       \
+      int occ = 0;                                                                            \
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                       \
+              &occ, reinterpret_cast<const void*>(k_solve<T, X, Y, Z>),                       \
+              TileShape<X, Y, Z>::THREADS, 0) != hipSuccess || occ < 1)                       \
+        occ = 1;                                                                              \
+      grid = h->persistent_grid(nt, occ);                                                     \
+    }                                                                                         \
+    hipLaunchKernelGGL((k_solve<T, X, Y, Z>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0, \
+                       s, h->d_pt(), tl, Uin, Uout, S, dt, dx, c, h->g, nt, h->mode >= 1);   \
+    return;                                                                                   \
+  }
+  switch (h->act) {
+    case 7: MHD_SHAPES_7(MHD_TRY) break;
+    case 3: MHD_SHAPES_3(MHD_TRY) break;
+    case 1: MHD_SHAPES_1(MHD_TRY) break;
+    case 6: MHD_SHAPES_6(MHD_TRY) break;
+    case 5: MHD_SHAPES_5(MHD_TRY) break;
+    case 2: MHD_SHAPES_2(MHD_TRY) break;
+    default: MHD_SHAPES_4(MHD_TRY) break;
+  }
+#undef MHD_TRY
 }
 
 template <typename T>
@@ -262,42 +514,56 @@ mhd_status launch_update(mhd_bunch* h, const T* Uin, T* Uout, const double* dt, 
                          hipStream_t s) {
   const Consts<T> c = h->consts<T>();
   T* S = (T*)h->d_scratch();
+  const int rm = h->mode >= 1;
   for (const auto& ch : h->chunks) {
     hipEvent_t t0;
-    if (ch.nblk[BOX_PRIM]) {
+    if (h->fused && ch.nptile) {
       t0 = h->tic(s);
-      hipLaunchKernelGGL(k_prim<T>, dim3(ch.nblk[BOX_PRIM]), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_PRIM) + ch.blk0[BOX_PRIM], Uin, S, c, h->g, h->d_status());
-      h->toc(s, MHD_KERNEL_PRIM, t0);
-    }
-    if (ch.nblk[BOX_EN]) {
-      t0 = h->tic(s);
-      hipLaunchKernelGGL(k_en<T>, dim3(ch.nblk[BOX_EN]), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_EN) + ch.blk0[BOX_EN], Uin, S, h->g);
-      h->toc(s, MHD_KERNEL_EDGE_EMF_N, t0);
-    }
-    if (ch.nblk[BOX_PRED]) {
-      t0 = h->tic(s);
-      hipLaunchKernelGGL(k_pred<T>, dim3(ch.nblk[BOX_PRED]), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], Uin, S, dt, dx, c, h->g);
+      const int nt = ch.nptile;
+      const TileDev* tl = h->d_ptiles() + ch.ptile0;
+#define MHD_PRED_LAUNCH(X, Y, Z)                                                                \
+  {                                                                                            \
+    int grid = nt;                                                                             \
+    if (h->mode == 2) {                                                                        \
+      int occ = 0;                                                                             \
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                        \
+              &occ, reinterpret_cast<const void*>(k_predict<T, X, Y, Z>),                      \
+              PredShape<X, Y, Z>::THREADS, 0) != hipSuccess || occ < 1)                        \
+        occ = 1;                                                                               \
+      grid = h->persistent_grid(nt, occ);                                                      \
+    }                                                                                          \
+    hipLaunchKernelGGL((k_predict<T, X, Y, Z>), dim3(grid), dim3(PredShape<X, Y, Z>::THREADS), 0, \
+                       s, h->d_pt(), tl, Uin, S, dt, dx, c, h->g, h->d_status(), nt, rm);      \
+  }
+      MHD_PRED_SHAPE(h->act, MHD_PRED_LAUNCH)
+#undef MHD_PRED_LAUNCH
       h->toc(s, MHD_KERNEL_PREDICT, t0);
     }
-    if (ch.ntile) {
+    if (!h->fused && ch.nblk[BOX_PRIM]) {
+      const int nb = ch.nblk[BOX_PRIM];
       t0 = h->tic(s);
-      const TileDev* tl = h->d_tiles() + ch.tile0;
-#define MHD_SOLVE(X, Y, Z)                                                                    \
-  hipLaunchKernelGGL((k_solve<T, X, Y, Z>), dim3(ch.ntile), dim3(TileShape<X, Y, Z>::THREADS), 0, \
-                     s, h->d_pt(), tl, Uin, Uout, (const T*)S, dt, dx, c, h->g)
-      switch (h->act) {
-        case 7: MHD_SOLVE(8, 8, 4); break;
-        case 3: MHD_SOLVE(16, 16, 1); break;
-        case 6: MHD_SOLVE(1, 16, 16); break;
-        case 5: MHD_SOLVE(16, 1, 16); break;
-        case 1: MHD_SOLVE(64, 1, 1); break;
-        case 2: MHD_SOLVE(1, 64, 1); break;
-        default: MHD_SOLVE(1, 1, 64); break;
-      }
-#undef MHD_SOLVE
+      hipLaunchKernelGGL(k_prim<T>, dim3(h->stage_grid(nb)), dim3(BLK), 0, s, h->d_pt(),
+                         h->d_blk(BOX_PRIM) + ch.blk0[BOX_PRIM], Uin, S, c, h->g, h->d_status(),
+                         nb, rm);
+      h->toc(s, MHD_KERNEL_PRIM, t0);
+    }
+    if (!h->fused && ch.nblk[BOX_EN]) {
+      const int nb = ch.nblk[BOX_EN];
+      t0 = h->tic(s);
+      hipLaunchKernelGGL(k_en<T>, dim3(h->stage_grid(nb)), dim3(BLK), 0, s, h->d_pt(),
+                         h->d_blk(BOX_EN) + ch.blk0[BOX_EN], Uin, S, h->g, nb, rm);
+      h->toc(s, MHD_KERNEL_EDGE_EMF_N, t0);
+    }
+    if (!h->fused && ch.nblk[BOX_PRED]) {
+      const int nb = ch.nblk[BOX_PRED];
+      t0 = h->tic(s);
+      hipLaunchKernelGGL(k_pred<T>, dim3(h->stage_grid(nb)), dim3(BLK), 0, s, h->d_pt(),
+                         h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], Uin, S, dt, dx, c, h->g, nb, rm);
+      h->toc(s, MHD_KERNEL_PREDICT, t0);
+    }
+    if (ch.ntile[h->shape]) {
+      t0 = h->tic(s);
+      launch_solve<T>(h, ch, Uin, Uout, (const T*)S, dt, dx, c, s);
       h->toc(s, MHD_KERNEL_SOLVE, t0);
     }
   }
@@ -327,6 +593,90 @@ mhd_status launch_guards(mhd_bunch* h, T* U, const int32_t* nbr, hipStream_t s) 
                      h->P, h->d_status());
   h->toc(s, MHD_KERNEL_GUARDS, t0);
   return h->hip_ok(hipGetLastError(), "launch guard kernel") ? MHD_OK : MHD_EDEVICE;
+}
+
+// owner -> guard-copies map of the whole bunch (empty when nbr is NULL: frozen guards)
+int build_guard_map(mhd_bunch* h, const int32_t* nbr) {
+  h->row.clear();
+  h->colp.clear();
+  h->colc.clear();
+  if (!nbr) return 0;
+  const int64_t ncell = h->state_elems / 8;
+  if (ncell >= INT32_MAX) return -1;
+  std::vector<int32_t> cnt(ncell + 1, 0);
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      h->row.assign(ncell + 1, 0);
+      for (int64_t i = 0; i < ncell; ++i) h->row[i + 1] = h->row[i] + cnt[i];
+      h->colp.assign(h->row[ncell], 0);
+      h->colc.assign(h->row[ncell], 0);
+      std::fill(cnt.begin(), cnt.end(), 0);
+    }
+    for (int p = 0; p < h->P; ++p) {
+      const PatchDev& P = h->pt[p];
+      for (int k = 0; k < P.N[2]; ++k)
+        for (int j = 0; j < P.N[1]; ++j)
+          for (int i = 0; i < P.N[0]; ++i) {
+            int src;
+            int64_t sc;
+            const int r = guard_source(h->pt.data(), p, h->g, i, j, k, nbr, h->P, src, sc);
+            if (r < 0) return -1;
+            if (r == 0) continue;
+            const int64_t id = h->pt[src].ubase / 8 + sc;
+            if (pass == 1) {
+              const int32_t at = h->row[id] + cnt[id];
+              h->colp[at] = p;
+              h->colc[at] = (int32_t)cell_of(P, i, j, k);
+            }
+            cnt[id]++;
+          }
+    }
+  }
+  return 0;
+}
+
+template <typename T>
+mhd_status launch_adjoint(mhd_bunch* h, const T* U, const T* lam, T* lam_in, const double* dt,
+                          const double* dx, hipStream_t s) {
+  const Consts<T> c = h->consts<T>();
+  T* S = (T*)h->d_scratch();
+  T* LS = (T*)(h->aws + h->a_ls);
+  T* LU = (T*)(h->aws + h->a_lu);
+  for (const auto& ch : h->chunks) {
+    // forward intermediates of this update (primitives, EMFs at t^n, predictor data)
+    if (ch.nblk[BOX_PRIM])
+      hipLaunchKernelGGL(k_prim<T>, dim3(ch.nblk[BOX_PRIM]), dim3(BLK), 0, s, h->d_pt(),
+                         h->d_blk(BOX_PRIM) + ch.blk0[BOX_PRIM], U, S, c, h->g, h->d_status(),
+                         ch.nblk[BOX_PRIM], 0);
+    if (ch.nblk[BOX_EN])
+      hipLaunchKernelGGL(k_en<T>, dim3(ch.nblk[BOX_EN]), dim3(BLK), 0, s, h->d_pt(),
+                         h->d_blk(BOX_EN) + ch.blk0[BOX_EN], U, S, h->g, ch.nblk[BOX_EN], 0);
+    if (ch.nblk[BOX_PRED])
+      hipLaunchKernelGGL(k_pred<T>, dim3(ch.nblk[BOX_PRED]), dim3(BLK), 0, s, h->d_pt(),
+                         h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], U, S, dt, dx, c, h->g,
+                         ch.nblk[BOX_PRED], 0);
+    // reverse sweep: predictor data, EMFs at t^n, primitives, padded input state
+    if (ch.nblk[BOX_PRED])
+      hipLaunchKernelGGL(k_adj_w<T>, dim3(ch.nblk[BOX_PRED], NW), dim3(BLK), 0, s, h->d_pt(),
+                         h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], (const T*)S, LS, lam, dt, dx, c, h->g, 0);
+    if (ch.nblk[BOX_EN])
+      hipLaunchKernelGGL(k_adj_e<T>, dim3(ch.nblk[BOX_EN], 3), dim3(BLK), 0, s, h->d_pt(),
+                         h->d_blk(BOX_EN) + ch.blk0[BOX_EN], U, (const T*)S, LS, dt, dx, c, h->g, 0);
+    if (ch.nblk[BOX_PRIM])
+      hipLaunchKernelGGL(k_adj_q<T>, dim3(ch.nblk[BOX_PRIM], 8), dim3(BLK), 0, s, h->d_pt(),
+                         h->d_blk(BOX_PRIM) + ch.blk0[BOX_PRIM], U, (const T*)S, LS, dt, dx, c, h->g, 0);
+    const int nb = ch.nblk_all;
+    if (nb)
+      hipLaunchKernelGGL(k_adj_u<T>, dim3(nb, 8), dim3(BLK), 0, s, h->d_pt(),
+                         h->d_blk(BOX_ALL) + ch.blk0_all, U, (const T*)S, (const T*)LS, lam, LU, dt,
+                         dx, c, h->g, 0);
+  }
+  const int nball = (int)h->blocks[BOX_ALL].size();
+  hipLaunchKernelGGL(k_adj_fold<T>, dim3(nball, 8), dim3(BLK), 0, s, h->d_pt(), h->d_blk(BOX_ALL),
+                     (const T*)LU, lam_in, (const int32_t*)(h->aws + h->a_row),
+                     (const int32_t*)(h->aws + h->a_colp), (const int32_t*)(h->aws + h->a_colc), h->g,
+                     h->adj_fold ? 1 : 0);
+  return h->hip_ok(hipGetLastError(), "launch adjoint kernels") ? MHD_OK : MHD_EDEVICE;
 }
 
 }  // namespace
@@ -426,7 +776,10 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
     base += 8 * P.Nc;
   }
   h->state_elems = base;
-  pick_tile(h);
+  set_shapes(h);
+#define MHD_SET_PRED(X, Y, Z) { h->PXs = X; h->PYs = Y; h->PZs = Z; }
+  MHD_PRED_SHAPE(h->act, MHD_SET_PRED)
+#undef MHD_SET_PRED
 
   // chunks of consecutive patches whose scratch fits the cap
   const int64_t esz = h->prec;
@@ -461,21 +814,41 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
       for (int p = ch.p0; p < ch.p1; ++p) add_blocks(h->blocks[kind], h->pt[p], p, kind, g);
       ch.nblk[kind] = (int)h->blocks[kind].size() - ch.blk0[kind];
     }
-    ch.tile0 = (int)h->tiles.size();
+    for (int k = 0; k < h->nshape; ++k) {
+      const TileCand tc = h->shapes[k];
+      const int T3[3] = {tc.x, tc.y, tc.z};
+      ch.tile0[k] = (int)h->tiles[k].size();
+      for (int p = ch.p0; p < ch.p1; ++p) {
+        const PatchDev& P = h->pt[p];
+        int nt[3];
+        for (int dd = 0; dd < 3; ++dd) nt[dd] = (P.act >> dd & 1) ? (P.n[dd] + T3[dd] - 1) / T3[dd] : 1;
+        for (int z = 0; z < nt[2]; ++z)
+          for (int y = 0; y < nt[1]; ++y)
+            for (int x = 0; x < nt[0]; ++x)
+              h->tiles[k].push_back(TileDev{p, x * tc.x, y * tc.y, z * tc.z});
+      }
+      ch.ntile[k] = (int)h->tiles[k].size() - ch.tile0[k];
+    }
+    ch.ptile0 = (int)h->ptiles.size();
     for (int p = ch.p0; p < ch.p1; ++p) {
       const PatchDev& P = h->pt[p];
-      const int T3[3] = {h->TX, h->TY, h->TZ};
+      const int T3[3] = {h->PXs, h->PYs, h->PZs};
       int nt[3];
-      for (int dd = 0; dd < 3; ++dd) nt[dd] = (P.act >> dd & 1) ? (P.n[dd] + T3[dd] - 1) / T3[dd] : 1;
+      for (int dd = 0; dd < 3; ++dd) nt[dd] = (P.act >> dd & 1) ? (P.n[dd] + 2 + T3[dd] - 1) / T3[dd] : 1;
       for (int z = 0; z < nt[2]; ++z)
         for (int y = 0; y < nt[1]; ++y)
-          for (int x = 0; x < nt[0]; ++x) h->tiles.push_back(TileDev{p, x * h->TX, y * h->TY, z * h->TZ});
+          for (int x = 0; x < nt[0]; ++x)
+            h->ptiles.push_back(TileDev{p, x * T3[0], y * T3[1], z * T3[2]});
     }
-    ch.ntile = (int)h->tiles.size() - ch.tile0;
+    ch.nptile = (int)h->ptiles.size() - ch.ptile0;
   }
-  for (int p = 0; p < h->P; ++p) {
-    add_blocks(h->blocks[BOX_INTERIOR], h->pt[p], p, BOX_INTERIOR, g);
-    add_blocks(h->blocks[BOX_ALL], h->pt[p], p, BOX_ALL, g);
+  for (auto& ch : h->chunks) {
+    ch.blk0_all = (int)h->blocks[BOX_ALL].size();
+    for (int p = ch.p0; p < ch.p1; ++p) {
+      add_blocks(h->blocks[BOX_INTERIOR], h->pt[p], p, BOX_INTERIOR, g);
+      add_blocks(h->blocks[BOX_ALL], h->pt[p], p, BOX_ALL, g);
+    }
+    ch.nblk_all = (int)h->blocks[BOX_ALL].size() - ch.blk0_all;
   }
   // workspace layout
   size_t o = 0;
@@ -485,8 +858,12 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
     h->o_blk[k] = o;
     o = align256(o + sizeof(BoxBlock) * std::max<size_t>(1, h->blocks[k].size()));
   }
-  h->o_tiles = o;
-  o = align256(o + sizeof(TileDev) * std::max<size_t>(1, h->tiles.size()));
+  for (int k = 0; k < h->nshape; ++k) {
+    h->o_tiles[k] = o;
+    o = align256(o + sizeof(TileDev) * std::max<size_t>(1, h->tiles[k].size()));
+  }
+  h->o_ptiles = o;
+  o = align256(o + sizeof(TileDev) * std::max<size_t>(1, h->ptiles.size()));
   h->o_smax = o;
   o = align256(o + sizeof(unsigned long long) * h->P);
   h->o_status = o;
@@ -512,6 +889,12 @@ mhd_status mhd_bunch_bind(mhd_bunch* h, void* ws, hipStream_t s) {
   if (!h || !ws || ((uintptr_t)ws & 255)) return MHD_EINVAL;
   h->ws = (char*)ws;
   h->last_error[0] = 0;
+  {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      h->ncu = n;
+  }
   bool ok = h->hip_ok(hipMemcpyAsync(h->ws + h->o_pt, h->pt.data(), sizeof(PatchDev) * h->P,
                                      hipMemcpyHostToDevice, s), "upload patch table");
   for (int k = 0; k < NBOX && ok; ++k)
@@ -519,9 +902,15 @@ mhd_status mhd_bunch_bind(mhd_bunch* h, void* ws, hipStream_t s) {
       ok = h->hip_ok(hipMemcpyAsync(h->ws + h->o_blk[k], h->blocks[k].data(),
                                     sizeof(BoxBlock) * h->blocks[k].size(), hipMemcpyHostToDevice, s),
                      "upload block table");
-  if (ok && !h->tiles.empty())
-    ok = h->hip_ok(hipMemcpyAsync(h->ws + h->o_tiles, h->tiles.data(), sizeof(TileDev) * h->tiles.size(),
-                                  hipMemcpyHostToDevice, s), "upload tile table");
+  if (ok && !h->ptiles.empty())
+    ok = h->hip_ok(hipMemcpyAsync(h->ws + h->o_ptiles, h->ptiles.data(),
+                                  sizeof(TileDev) * h->ptiles.size(), hipMemcpyHostToDevice, s),
+                   "upload predictor tile table");
+  for (int k = 0; k < h->nshape && ok; ++k)
+    if (!h->tiles[k].empty())
+      ok = h->hip_ok(hipMemcpyAsync(h->ws + h->o_tiles[k], h->tiles[k].data(),
+                                    sizeof(TileDev) * h->tiles[k].size(), hipMemcpyHostToDevice, s),
+                     "upload tile table");
   if (ok) {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, (unsigned long long*)(h->ws + h->o_status), 1);
     ok = h->hip_ok(hipGetLastError(), "clear status word");
@@ -534,6 +923,55 @@ mhd_status mhd_bunch_bind(mhd_bunch* h, void* ws, hipStream_t s) {
 }
 
 const char* mhd_bunch_last_error(const mhd_bunch* h) { return h ? h->last_error : "null handle"; }
+
+int64_t mhd_bunch_adjoint_workspace_bytes(mhd_bunch* h, const int32_t* nbr_host) {
+  if (!h) return -1;
+  if (build_guard_map(h, nbr_host) != 0) return -1;
+  size_t o = 0;
+  h->a_ls = o;
+  o = align256(o + (size_t)h->scratch_elems * h->prec);
+  h->a_lu = o;
+  o = align256(o + (size_t)h->state_elems * h->prec);
+  h->a_row = o;
+  o = align256(o + sizeof(int32_t) * std::max<size_t>(1, h->row.size()));
+  h->a_colp = o;
+  o = align256(o + sizeof(int32_t) * std::max<size_t>(1, h->colp.size()));
+  h->a_colc = o;
+  o = align256(o + sizeof(int32_t) * std::max<size_t>(1, h->colc.size()));
+  h->a_bytes = o;
+  return (int64_t)o;
+}
+
+mhd_status mhd_bunch_adjoint_bind(mhd_bunch* h, const int32_t* nbr_host, void* ws, hipStream_t s) {
+  if (!h || !ws || ((uintptr_t)ws & 255)) return MHD_EINVAL;
+  if (!h->bound) return MHD_ESTATE;
+  if (mhd_bunch_adjoint_workspace_bytes(h, nbr_host) < 0) return MHD_EINVAL;
+  h->aws = (char*)ws;
+  h->adj_fold = nbr_host != nullptr;
+  bool ok = true;
+  if (h->adj_fold) {
+    ok = h->hip_ok(hipMemcpyAsync(h->aws + h->a_row, h->row.data(), sizeof(int32_t) * h->row.size(),
+                                  hipMemcpyHostToDevice, s), "upload guard map");
+    if (ok && !h->colp.empty())
+      ok = h->hip_ok(hipMemcpyAsync(h->aws + h->a_colp, h->colp.data(), sizeof(int32_t) * h->colp.size(),
+                                    hipMemcpyHostToDevice, s), "upload guard map") &&
+           h->hip_ok(hipMemcpyAsync(h->aws + h->a_colc, h->colc.data(), sizeof(int32_t) * h->colc.size(),
+                                    hipMemcpyHostToDevice, s), "upload guard map");
+    if (ok) ok = h->hip_ok(hipStreamSynchronize(s), "synchronise after upload");
+  }
+  if (!ok) return MHD_EDEVICE;
+  h->adj_bound = true;
+  return MHD_OK;
+}
+
+mhd_status mhd_bunch_adjoint(mhd_bunch* h, const void* U_in, const void* lam_out, void* lam_in,
+                             const double* dt, const double* dx, hipStream_t s) {
+  if (!h || !U_in || !lam_out || !lam_in || !dt || !dx || lam_in == lam_out) return MHD_EINVAL;
+  if (!h->bound || !h->adj_bound) return MHD_ESTATE;
+  return h->prec == 8
+             ? launch_adjoint<double>(h, (const double*)U_in, (const double*)lam_out, (double*)lam_in, dt, dx, s)
+             : launch_adjoint<float>(h, (const float*)U_in, (const float*)lam_out, (float*)lam_in, dt, dx, s);
+}
 
 mhd_status mhd_bunch_load(mhd_bunch* h, void* U, int32_t p, const void* src, int32_t src_dev,
                           hipStream_t s) {
@@ -595,6 +1033,139 @@ mhd_status mhd_bunch_check(mhd_bunch* h, hipStream_t s) {
     return (st & 2) ? MHD_EINVAL : MHD_ENONPHYS;
   }
   return MHD_OK;
+}
+
+int32_t mhd_bunch_tile_count(const mhd_bunch* h) { return h ? NMODE * h->nshape : -1; }
+
+int32_t mhd_bunch_tile_current(const mhd_bunch* h) { return h ? NMODE * h->shape + h->mode : -1; }
+
+mhd_status mhd_bunch_tile_get(const mhd_bunch* h, int32_t idx, int32_t cfg[4]) {
+  if (!h || !cfg || idx < 0 || idx >= NMODE * h->nshape) return MHD_EINVAL;
+  const TileCand tc = h->shapes[idx / NMODE];
+  cfg[0] = tc.x;
+  cfg[1] = tc.y;
+  cfg[2] = tc.z;
+  cfg[3] = idx % NMODE;
+  return MHD_OK;
+}
+
+mhd_status mhd_bunch_tile_set(mhd_bunch* h, int32_t idx) {
+  if (!h || idx < 0 || idx >= NMODE * h->nshape) return MHD_EINVAL;
+  h->shape = idx / NMODE;
+  h->mode = idx % NMODE;
+  return MHD_OK;
+}
+
+mhd_status mhd_bunch_set_predictor(mhd_bunch* h, int32_t fused) {
+  if (!h || (fused != 0 && fused != 1)) return MHD_EINVAL;
+  h->fused = fused;
+  return MHD_OK;
+}
+
+int32_t mhd_bunch_predictor(const mhd_bunch* h) { return h ? h->fused : -1; }
+
+mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* Uin, void* Uout, const double* dt,
+                              const double* dx, int32_t reps, hipStream_t s, int32_t* best,
+                              float* ms) {
+  if (!h || !Uin || !Uout || !dt || !dx || reps < 1 || Uin == Uout) return MHD_EINVAL;
+  if (!h->bound) return MHD_ESTATE;
+  const int n = NMODE * h->nshape;
+  const bool prof = h->prof;
+  h->prof = false;
+  hipEvent_t a = nullptr, b = nullptr;
+  bool ok = h->hip_ok(hipEventCreate(&a), "autotune event") && h->hip_ok(hipEventCreate(&b), "autotune event");
+  int bi = 0;
+  float bms = 0.0f;
+  for (int k = 0; k < n && ok; ++k) {
+    h->shape = k / NMODE;
+    h->mode = k % NMODE;
+    ok = mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;  // warm-up
+    ok = ok && h->hip_ok(hipEventRecord(a, s), "autotune event");
+    for (int r = 0; r < reps && ok; ++r) ok = mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;
+    ok = ok && h->hip_ok(hipEventRecord(b, s), "autotune event") &&
+         h->hip_ok(hipEventSynchronize(b), "autotune sync");
+    float t = 0.0f;
+    ok = ok && h->hip_ok(hipEventElapsedTime(&t, a, b), "autotune timing");
+    t /= reps;
+    if (ms) ms[k] = t;
+    if (ok && (k == 0 || t < bms)) {
+      bi = k;
+      bms = t;
+    }
+  }
+  h->shape = bi / NMODE;
+  h->mode = bi % NMODE;
+  // predictor: staged kernels or the fused tile kernel, with the chosen configuration
+  const int f0 = h->fused;
+  float fms[2] = {0.0f, 0.0f};
+  for (int f = 0; f < 2 && ok; ++f) {
+    h->fused = f;
+    ok = mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;
+    ok = ok && h->hip_ok(hipEventRecord(a, s), "autotune event");
+    for (int r = 0; r < reps && ok; ++r) ok = mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;
+    ok = ok && h->hip_ok(hipEventRecord(b, s), "autotune event") &&
+         h->hip_ok(hipEventSynchronize(b), "autotune sync") &&
+         h->hip_ok(hipEventElapsedTime(&fms[f], a, b), "autotune timing");
+  }
+  h->fused = ok ? (fms[1] < fms[0] ? 1 : 0) : f0;
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  h->prof = prof;
+  if (best) *best = bi;
+  return ok ? MHD_OK : MHD_EDEVICE;
+}
+
+mhd_status mhd_bunch_graph_capture(mhd_bunch* h, int32_t nsteps, void* U_a, void* U_b, double* dt,
+                                   const double* dx, const int32_t* nbr, int32_t dt_mode,
+                                   hipStream_t s) {
+  (void)s;
+  if (!h || nsteps < 1 || !U_a || !U_b || !dt || !dx || dt_mode < 0 || dt_mode > 2) return MHD_EINVAL;
+  if (!h->bound) return MHD_ESTATE;
+  const size_t bytes = (size_t)h->state_elems * h->prec;
+  const char *pa = (const char*)U_a, *pb = (const char*)U_b;
+  if (pa < pb + bytes && pb < pa + bytes) return MHD_EINVAL;
+  h->drop_graph();
+  // captured on a private stream: the caller's may be the null stream, which cannot be
+  // captured; the graph is later launched on the caller's stream
+  hipStream_t cs = nullptr;
+  if (!h->hip_ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream"))
+    return MHD_EDEVICE;
+  const bool prof = h->prof;
+  h->prof = false;
+  mhd_status st = MHD_OK;
+  if (!h->hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture")) {
+    st = MHD_EDEVICE;
+  } else {
+    for (int k = 0; k < nsteps && st == MHD_OK; ++k) {
+      void* in = (k % 2 == 0) ? U_a : U_b;
+      void* out = (k % 2 == 0) ? U_b : U_a;
+      if (nbr) st = mhd_bunch_fill_guards(h, in, nbr, cs);
+      if (st == MHD_OK && dt_mode) st = mhd_bunch_cfl(h, in, dx, dt, dt_mode == 2, cs);
+      if (st == MHD_OK) st = mhd_bunch_update(h, in, out, dt, dx, cs);
+    }
+    hipGraph_t g = nullptr;
+    const bool ended = h->hip_ok(hipStreamEndCapture(cs, &g), "end capture");
+    if (st == MHD_OK && !ended) st = MHD_EDEVICE;
+    if (st == MHD_OK) {
+      h->graph = g;
+      if (!h->hip_ok(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0), "instantiate graph")) {
+        h->gexec = nullptr;
+        st = MHD_EDEVICE;
+      }
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  h->prof = prof;
+  (void)hipStreamDestroy(cs);
+  if (st != MHD_OK) h->drop_graph();
+  return st;
+}
+
+mhd_status mhd_bunch_graph_launch(mhd_bunch* h, hipStream_t s) {
+  if (!h) return MHD_EINVAL;
+  if (!h->gexec) return MHD_ESTATE;
+  return h->hip_ok(hipGraphLaunch(h->gexec, s), "graph launch") ? MHD_OK : MHD_EDEVICE;
 }
 
 }  // extern "C"

@@ -15,8 +15,126 @@ __host__ __device__ __forceinline__ float m_min(float a, float b) { return fminf
 __host__ __device__ __forceinline__ double m_min(double a, double b) { return fmin(a, b); }
 __host__ __device__ __forceinline__ float m_max(float a, float b) { return fmaxf(a, b); }
 __host__ __device__ __forceinline__ double m_max(double a, double b) { return fmax(a, b); }
-__host__ __device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
-__host__ __device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+
+// Reciprocal, square root and reciprocal square root.  The update takes them of nonzero
+// finite numbers (densities and pressures after the floors, wave-speed sums bounded below)
+// and of zero only in m_sqrt.  On the device they are built on the CDNA hardware
+// approximations instead of the IEEE-exact library sequences (which spend 10-17
+// instructions on scaling and special cases):
+//  float : v_rcp_f32 / v_sqrt_f32 / v_rsq_f32 as they are (about 1 ulp);
+//  double: v_rcp_f64 / v_rsq_f64 seeds refined by Newton-Raphson (reciprocal: two
+//          iterations of r <- r + r (1 - x r); square root: the coupled iteration for
+//          g ~ sqrt(x), h ~ 1 / (2 sqrt(x)) with one residual correction), within about
+//          1 ulp of the exact result.
+// The host versions (CPU builds of this header) are the plain operations.
+__host__ __device__ __forceinline__ float m_rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+__host__ __device__ __forceinline__ double m_rcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+__host__ __device__ __forceinline__ float m_sqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_sqrtf(x);
+#else
+  return sqrtf(x);
+#endif
+}
+__host__ __device__ __forceinline__ double m_sqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  g = fma(h, d, g);
+  return x > 0.0 ? g : 0.0;
+#else
+  return sqrt(x);
+#endif
+}
+__host__ __device__ __forceinline__ float m_rsqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rsqf(x);
+#else
+  return 1.0f / sqrtf(x);
+#endif
+}
+__host__ __device__ __forceinline__ double m_rsqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+
+// Forward-mode dual number (value, derivative along one seeded input).  The pointwise
+// functions below are templates on the scalar, so the same code yields derivatives when
+// instantiated with Dual<T>; the adjoint kernels use this to differentiate every stage.
+template <typename T>
+struct Dual {
+  T v, d;
+  __host__ __device__ __forceinline__ Dual() : v(T(0)), d(T(0)) {}
+  __host__ __device__ __forceinline__ Dual(T a) : v(a), d(T(0)) {}
+  __host__ __device__ __forceinline__ Dual(T a, T b) : v(a), d(b) {}
+  __host__ __device__ __forceinline__ Dual& operator+=(const Dual& o) { v += o.v; d += o.d; return *this; }
+};
+template <typename T>
+__host__ __device__ __forceinline__ Dual<T> operator+(Dual<T> a, Dual<T> b) { return Dual<T>(a.v + b.v, a.d + b.d); }
+template <typename T>
+__host__ __device__ __forceinline__ Dual<T> operator-(Dual<T> a, Dual<T> b) { return Dual<T>(a.v - b.v, a.d - b.d); }
+template <typename T>
+__host__ __device__ __forceinline__ Dual<T> operator-(Dual<T> a) { return Dual<T>(-a.v, -a.d); }
+template <typename T>
+__host__ __device__ __forceinline__ Dual<T> operator*(Dual<T> a, Dual<T> b) {
+  return Dual<T>(a.v * b.v, a.d * b.v + a.v * b.d);
+}
+template <typename T>
+__host__ __device__ __forceinline__ Dual<T> m_rcp(Dual<T> x) {
+  const T r = m_rcp(x.v);
+  return Dual<T>(r, -(x.d * r) * r);
+}
+template <typename T>
+__host__ __device__ __forceinline__ bool operator<(Dual<T> a, Dual<T> b) { return a.v < b.v; }
+template <typename T>
+__host__ __device__ __forceinline__ bool operator>(Dual<T> a, Dual<T> b) { return a.v > b.v; }
+template <typename T>
+__host__ __device__ __forceinline__ bool operator<=(Dual<T> a, Dual<T> b) { return a.v <= b.v; }
+template <typename T>
+__host__ __device__ __forceinline__ bool operator>=(Dual<T> a, Dual<T> b) { return a.v >= b.v; }
+template <typename T>
+__host__ __device__ __forceinline__ Dual<T> m_abs(Dual<T> x) { return x.v < T(0) ? -x : x; }
+template <typename T>
+__host__ __device__ __forceinline__ Dual<T> m_min(Dual<T> a, Dual<T> b) { return b.v < a.v ? b : a; }
+template <typename T>
+__host__ __device__ __forceinline__ Dual<T> m_max(Dual<T> a, Dual<T> b) { return a.v < b.v ? b : a; }
+template <typename T>
+__host__ __device__ __forceinline__ Dual<T> m_sqrt(Dual<T> x) {
+  const T s = m_sqrt(x.v);
+  return Dual<T>(s, x.d * (T(0.5) * m_rcp(s)));
+}
+template <typename T>
+__host__ __device__ __forceinline__ Dual<T> m_rsqrt(Dual<T> x) {
+  const T y = m_rsqrt(x.v);
+  return Dual<T>(y, (T(-0.5) * x.d) * (y * y * y));
+}
 
 template <typename T>
 struct Consts {
@@ -29,6 +147,21 @@ struct Consts {
   T tiny;       // guard of the EMF denominators
   int limiter;  // 0 monotonised central, 1 minmod
 };
+
+// constants of one scalar type converted to another (e.g. T -> Dual<T>)
+template <typename S, typename T>
+__host__ __device__ __forceinline__ Consts<S> lift(const Consts<T>& c) {
+  Consts<S> o;
+  o.gamma = S(c.gamma);
+  o.gm1 = S(c.gm1);
+  o.inv_gm1 = S(c.inv_gm1);
+  o.rho_floor = S(c.rho_floor);
+  o.p_floor = S(c.p_floor);
+  o.eps_deg = S(c.eps_deg);
+  o.tiny = S(c.tiny);
+  o.limiter = c.limiter;
+  return o;
+}
 
 // Limited slope from the backward and forward differences (§2.1 "The MUSCL Scheme": the
 // slope estimate must suppress oscillations).  Zero unless both differences share a
@@ -43,46 +176,65 @@ __host__ __device__ __forceinline__ T limited_slope(T dm, T dp, int kind) {
 }
 
 // Fast magnetosonic speed along a direction with normal field bn; the radicand is the
-// cancellation-free (a^2 - b^2)^2 + 4 a^2 b_t^2 / rho.
+// cancellation-free (a^2 - b^2)^2 + 4 a^2 b_t^2 / rho.  The direction-independent part
+// (1/rho, a^2, b^2 = |B|^2/rho) is split off so that the two directions of one state
+// share it.
+template <typename T>
+struct WaveBase {
+  T ir, a2, b2, d2;
+};
+template <typename T>
+__host__ __device__ __forceinline__ WaveBase<T> wave_base(T rho, T p, T bsq, T gamma) {
+  WaveBase<T> w;
+  w.ir = m_rcp(rho);
+  w.a2 = gamma * p * w.ir;
+  w.b2 = bsq * w.ir;
+  const T d = w.a2 - w.b2;
+  w.d2 = d * d;
+  return w;
+}
+template <typename T>
+__host__ __device__ __forceinline__ T fast_speed_t(const WaveBase<T>& w, T bt) {
+  const T rad = w.d2 + T(4) * w.a2 * (bt * w.ir);
+  return m_sqrt(T(0.5) * (w.a2 + w.b2 + m_sqrt(rad)));
+}
 template <typename T>
 __host__ __device__ __forceinline__ T fast_speed(T rho, T p, T bn, T bt1, T bt2, T gamma) {
-  const T ir = T(1) / rho;
-  const T a2 = gamma * p * ir;
   const T bt = bt1 * bt1 + bt2 * bt2;
-  const T b2 = (bn * bn + bt) * ir;
-  const T d = a2 - b2;
-  const T rad = d * d + T(4) * a2 * (bt * ir);
-  return m_sqrt(T(0.5) * (a2 + b2 + m_sqrt(rad)));
+  return fast_speed_t(wave_base(rho, p, bn * bn + bt, gamma), bt);
 }
 
 // d(q)/dt of ideal MHD in primitive variables q = (rho, u, v, w, p, Bx, By, Bz) from
-// spatial derivatives G[d][m] (rows of collapsed directions are zero).  The induction
+// slopes D[d][m] and inverse cell sizes ix[d] (rows of collapsed directions are zero).  The induction
 // equation is taken in its div B = 0 form.  Forward-Euler half step of the predictor.
 template <typename T>
-__host__ __device__ __forceinline__ void prim_rate(const T q[8], const T G[3][8], T gamma,
-                                                   T r[8]) {
+__host__ __device__ __forceinline__ void prim_rate(const T q[8], const T D[3][8], const T ix[3],
+                                                   T gamma, T r[8]) {
+  // spatial derivative of primitive m along d: the slope over the cell size
+#define MHD_G(d, m) (D[d][m] * ix[d])
   const T rho = q[0], p = q[4];
-  const T ir = T(1) / rho;
-  const T div = G[0][1] + G[1][2] + G[2][3];
+  const T ir = m_rcp(rho);
+  const T div = MHD_G(0, 1) + MHD_G(1, 2) + MHD_G(2, 3);
   T ar = T(0), ap = T(0);
   for (int d = 0; d < 3; ++d) {
-    ar += q[1 + d] * G[d][0];
-    ap += q[1 + d] * G[d][4];
+    ar += q[1 + d] * MHD_G(d, 0);
+    ap += q[1 + d] * MHD_G(d, 4);
   }
   r[0] = -(ar + rho * div);
   r[4] = -(ap + gamma * p * div);
   for (int i = 0; i < 3; ++i) {
     T adv = T(0), ten = T(0), str = T(0), advb = T(0);
     for (int d = 0; d < 3; ++d) {
-      adv += q[1 + d] * G[d][1 + i];
-      ten += q[5 + d] * G[d][5 + i];
-      str += q[5 + d] * G[d][1 + i];
-      advb += q[1 + d] * G[d][5 + i];
+      adv += q[1 + d] * MHD_G(d, 1 + i);
+      ten += q[5 + d] * MHD_G(d, 5 + i);
+      str += q[5 + d] * MHD_G(d, 1 + i);
+      advb += q[1 + d] * MHD_G(d, 5 + i);
     }
-    const T grad = G[i][4] + (q[5] * G[i][5] + q[6] * G[i][6] + q[7] * G[i][7]);
+    const T grad = MHD_G(i, 4) + (q[5] * MHD_G(i, 5) + q[6] * MHD_G(i, 6) + q[7] * MHD_G(i, 7));
     r[1 + i] = -adv - (grad - ten) * ir;
     r[5 + i] = str - advb - q[5 + i] * div;
   }
+#undef MHD_G
 }
 
 // HLLD flux through a face (§2.1 "HLLD Solver", Fig. 1; Miyoshi & Kusano 2005).
@@ -108,19 +260,19 @@ __host__ __device__ __forceinline__ void hlld_flux(const T s[2][7], T bn, const 
   const T S[2] = {m_min(s[0][1], s[1][1]) - cmx, m_max(s[0][1], s[1][1]) + cmx};
   const T sd[2] = {S[0] - s[0][1], S[1] - s[1][1]};     // S_a - u_a
   const T mf[2] = {sd[0] * s[0][0], sd[1] * s[1][0]};   // rho_a (S_a - u_a)
-  const T iden = T(1) / (mf[1] - mf[0]);
+  const T iden = m_rcp(mf[1] - mf[0]);
   const T sm = (mf[1] * s[1][1] - mf[0] * s[0][1] - pt[1] + pt[0]) * iden;
   const T pts = (mf[1] * pt[0] - mf[0] * pt[1] + mf[0] * mf[1] * (s[1][1] - s[0][1])) * iden;
 
   // single-star states
   T rs[2], vs[2], ws[2], bys[2], bzs[2], es[2], ubs[2];
   for (int k = 0; k < 2; ++k) {
-    const T isd = T(1) / (S[k] - sm);
+    const T isd = m_rcp(S[k] - sm);
     rs[k] = mf[k] * isd;
     const T dd = mf[k] * (S[k] - sm) - bn2;
     const T qq = mf[k] * sd[k] - bn2;
     if (m_abs(dd) > c.eps_deg * (mf[k] * sd[k] + bn2)) {
-      const T idd = T(1) / dd;
+      const T idd = m_rcp(dd);
       const T tv = bn * (sm - s[k][1]) * idd;
       const T tb = qq * idd;
       vs[k] = s[k][2] - s[k][5] * tv;
@@ -138,11 +290,12 @@ __host__ __device__ __forceinline__ void hlld_flux(const T s[2][7], T bn, const 
   }
 
   // rotational (Alfven) discontinuities and the double-star state
-  const T sq[2] = {m_sqrt(rs[0]), m_sqrt(rs[1])};
+  const T isq[2] = {m_rsqrt(rs[0]), m_rsqrt(rs[1])};
+  const T sq[2] = {rs[0] * isq[0], rs[1] * isq[1]};
   const T abn = m_abs(bn);
-  const T Ss[2] = {sm - abn / sq[0], sm + abn / sq[1]};
+  const T Ss[2] = {sm - abn * isq[0], sm + abn * isq[1]};
   const T sg = bn < T(0) ? T(-1) : T(1);
-  const T isum = T(1) / (sq[0] + sq[1]);
+  const T isum = m_rcp(sq[0] + sq[1]);
   const T vss = (sq[0] * vs[0] + sq[1] * vs[1] + (bys[1] - bys[0]) * sg) * isum;
   const T wss = (sq[0] * ws[0] + sq[1] * ws[1] + (bzs[1] - bzs[0]) * sg) * isum;
   const T byss = (sq[0] * bys[1] + sq[1] * bys[0] + sq[0] * sq[1] * (vs[1] - vs[0]) * sg) * isum;
@@ -193,8 +346,10 @@ __host__ __device__ __forceinline__ T uct_emf(const T C[4][7], const Consts<T>& 
     const T r = C[k][0], ua = C[k][1], ubb = C[k][2], p = C[k][3];
     const T be = C[k][4], ba = C[k][5], bb = C[k][6];
     emf[k] = ua * bb - ubb * ba;
-    const T cfa = fast_speed(r, p, ba, bb, be, c.gamma);
-    const T cfb = fast_speed(r, p, bb, be, ba, c.gamma);
+    const T ba2 = ba * ba, bb2 = bb * bb, be2 = be * be;
+    const WaveBase<T> wb = wave_base(r, p, ba2 + bb2 + be2, c.gamma);
+    const T cfa = fast_speed_t(wb, bb2 + be2);
+    const T cfb = fast_speed_t(wb, be2 + ba2);
     apa = m_max(apa, ua + cfa);
     ama = m_max(ama, cfa - ua);
     apb = m_max(apb, ubb + cfb);
@@ -203,9 +358,10 @@ __host__ __device__ __forceinline__ T uct_emf(const T C[4][7], const Consts<T>& 
   const T da = m_max(apa + ama, c.tiny);
   const T db = m_max(apb + amb, c.tiny);
   // corners: 0 SW, 1 SE, 2 NW, 3 NE
-  const T avg = (apa * apb * emf[0] + apa * amb * emf[2] + ama * apb * emf[1] + ama * amb * emf[3]) /
-                (da * db);
-  return avg - apa * ama / da * (C[1][6] - C[0][6]) + apb * amb / db * (C[2][5] - C[0][5]);
+  const T ida = m_rcp(da), idb = m_rcp(db);
+  const T avg = (apa * apb * emf[0] + apa * amb * emf[2] + ama * apb * emf[1] + ama * amb * emf[3]) *
+                (ida * idb);
+  return avg - apa * ama * ida * (C[1][6] - C[0][6]) + apb * amb * idb * (C[2][5] - C[0][5]);
 }
 
 }  // namespace mhd

@@ -88,187 +88,238 @@ __host__ __device__ __forceinline__ int dbf_slot(int d, int e) {
   return W_DB + 2 * d + (e == (d + 1) % 3 ? 0 : 1);
 }
 
-// ---------------------------------------------------------------- stage 1: primitives
-// Returns 1 if the conserved state is not physical (rho <= 0, p <= 0 or NaN).
+// Loads: every stage reads its inputs through an accessor taking the absolute element
+// index of the array, so the same code runs on plain values (Ld) or on dual numbers with one
+// seeded input element (LdSeed, used by the adjoint).
 template <typename T>
-__host__ __device__ __forceinline__ int prim_item(const PatchDev& P, int64_t cell, const T* U,
-                                                  T* S, const Consts<T>& c) {
-  const int64_t Nc = P.Nc;
-  const T* u = U + P.ubase;
-  T rho = u[cell];
-  const T mx = u[Nc + cell], my = u[2 * Nc + cell], mz = u[3 * Nc + cell], en = u[4 * Nc + cell];
-  const T bx = T(0.5) * (u[5 * Nc + cell] + u[5 * Nc + cell + P.off[0]]);
-  const T by = T(0.5) * (u[6 * Nc + cell] + u[6 * Nc + cell + P.off[1]]);
-  const T bz = T(0.5) * (u[7 * Nc + cell] + u[7 * Nc + cell + P.off[2]]);
-  int bad = !(rho > T(0));
+struct Ld {
+  const T* p;
+  __host__ __device__ __forceinline__ T operator()(int64_t i) const { return p[i]; }
+};
+
+template <typename T>
+struct LdSeed {
+  const T* p;
+  int64_t seed;  // element whose derivative is taken (-1: none)
+  __host__ __device__ __forceinline__ Dual<T> operator()(int64_t i) const {
+    return Dual<T>(p[i], i == seed ? T(1) : T(0));
+  }
+};
+
+// ---------------------------------------------------------------- stage 1: primitives
+// Primitives of padded cell `cell` from U (absolute indices through u).  Returns 1 if the
+// conserved state is not physical (rho <= 0, p <= 0 or NaN).
+template <typename S, class AU>
+__host__ __device__ __forceinline__ int prim_point(const PatchDev& P, int64_t cell, const AU& u,
+                                                   const Consts<S>& c, S q[8]) {
+  const int64_t Nc = P.Nc, b = P.ubase + cell;
+  S rho = u(b);
+  const S mx = u(b + Nc), my = u(b + 2 * Nc), mz = u(b + 3 * Nc), en = u(b + 4 * Nc);
+  const S bx = S(0.5) * (u(b + 5 * Nc) + u(b + 5 * Nc + P.off[0]));
+  const S by = S(0.5) * (u(b + 6 * Nc) + u(b + 6 * Nc + P.off[1]));
+  const S bz = S(0.5) * (u(b + 7 * Nc) + u(b + 7 * Nc + P.off[2]));
+  int bad = !(rho > S(0));
   if (rho < c.rho_floor) rho = c.rho_floor;
-  const T ir = T(1) / rho;
-  const T vx = mx * ir, vy = my * ir, vz = mz * ir;
-  T p = c.gm1 * (en - T(0.5) * rho * (vx * vx + vy * vy + vz * vz) -
-                 T(0.5) * (bx * bx + by * by + bz * bz));
-  bad |= !(p > T(0));
+  const S ir = m_rcp(rho);
+  const S vx = mx * ir, vy = my * ir, vz = mz * ir;
+  S p = c.gm1 * (en - S(0.5) * rho * (vx * vx + vy * vy + vz * vz) -
+                 S(0.5) * (bx * bx + by * by + bz * bz));
+  bad |= !(p > S(0));
   if (p < c.p_floor) p = c.p_floor;
-  T* q = S + P.sbase;
-  q[cell] = rho;
-  q[Nc + cell] = vx;
-  q[2 * Nc + cell] = vy;
-  q[3 * Nc + cell] = vz;
-  q[4 * Nc + cell] = p;
-  q[5 * Nc + cell] = bx;
-  q[6 * Nc + cell] = by;
-  q[7 * Nc + cell] = bz;
+  q[0] = rho; q[1] = vx; q[2] = vy; q[3] = vz;
+  q[4] = p; q[5] = bx; q[6] = by; q[7] = bz;
   return bad;
 }
 
 // ------------------------------------------------- stage 2: edge EMFs at time n
-template <typename T>
-__host__ __device__ __forceinline__ void en_item(const PatchDev& P, int64_t cell, const T* U, T* S) {
-  const int64_t Nc = P.Nc;
-  const T* u = U + P.ubase;
-  const T* q = S + P.sbase;
-  T* E = S + P.sbase + 8 * Nc;
+// E_e at the edge along e of padded cell `cell` (corner (-1/2, -1/2) in the cyclic (a, b)
+// plane): 4-cell average velocities, 2-face average fields.  q reads primitives (absolute
+// index P.sbase + m Nc + cell), u reads U.
+template <typename S, class AQ, class AU>
+__host__ __device__ __forceinline__ void en_point(const PatchDev& P, int64_t cell, const AQ& q,
+                                                  const AU& u, S E[3]) {
+  const int64_t Nc = P.Nc, qb = P.sbase + cell, ub = P.ubase + cell;
   for (int e = 0; e < 3; ++e) {
     const int a = (e + 1) % 3, b = (e + 2) % 3;
     const int64_t oa = P.off[a], ob = P.off[b];
-    const T* qa = q + (1 + a) * Nc;
-    const T* qb = q + (1 + b) * Nc;
-    const T va = T(0.25) * (qa[cell] + qa[cell - oa] + qa[cell - ob] + qa[cell - oa - ob]);
-    const T vb = T(0.25) * (qb[cell] + qb[cell - oa] + qb[cell - ob] + qb[cell - oa - ob]);
-    const T ba = T(0.5) * (u[(5 + a) * Nc + cell] + u[(5 + a) * Nc + cell - ob]);
-    const T bb = T(0.5) * (u[(5 + b) * Nc + cell] + u[(5 + b) * Nc + cell - oa]);
-    E[e * Nc + cell] = va * bb - vb * ba;
+    const int64_t qa = qb + (1 + a) * Nc, qbb = qb + (1 + b) * Nc;
+    const S va = S(0.25) * (q(qa) + q(qa - oa) + q(qa - ob) + q(qa - oa - ob));
+    const S vb = S(0.25) * (q(qbb) + q(qbb - oa) + q(qbb - ob) + q(qbb - oa - ob));
+    const S ba = S(0.5) * (u(ub + (5 + a) * Nc) + u(ub + (5 + a) * Nc - ob));
+    const S bb = S(0.5) * (u(ub + (5 + b) * Nc) + u(ub + (5 + b) * Nc - oa));
+    E[e] = va * bb - vb * ba;
   }
 }
 
 // ------------------------------------------------------ stage 3: predictor data
-template <typename T>
-__host__ __device__ __forceinline__ void pred_item(const PatchDev& P, int g, int i, int j, int k,
-                                                   const T* U, const T* S, T* Wout, double dt,
-                                                   const double* dxp, const Consts<T>& c) {
+// The 38 predictor values of padded cell (i, j, k): q + dt/2 dq/dt, limited slopes, half-step
+// field on the three lower faces, transverse slopes of those face fields.  q reads the
+// primitives, e the edge EMFs (absolute index P.sbase + 8 Nc + e Nc + cell), u reads U.
+template <typename S, class AU, class AQ, class AE>
+__host__ __device__ __forceinline__ void pred_point(const PatchDev& P, int i, int j, int k,
+                                                    const AU& u, const AQ& q, const AE& e,
+                                                    double dt, const double* dxp,
+                                                    const Consts<S>& c, S w[NW]) {
   const int64_t Nc = P.Nc;
   const int64_t cell = cell_of(P, i, j, k);
-  const T* u = U + P.ubase;
-  const T* q = S + P.sbase;
-  const T* E = S + P.sbase + 8 * Nc;
-  T qc[8];
-  for (int m = 0; m < 8; ++m) qc[m] = q[m * Nc + cell];
-  T D[3][8];
-  T G[3][8];
+  const int64_t qb = P.sbase + cell, ub = P.ubase + cell, eb = P.sbase + 8 * Nc + cell;
+  S qc[8];
+  for (int m = 0; m < 8; ++m) qc[m] = q(qb + m * Nc);
+  S D[3][8];
+  S ix[3];
   for (int d = 0; d < 3; ++d) {
+    ix[d] = S(1.0 / dxp[d]);
     if (!active(P, d)) {
-      for (int m = 0; m < 8; ++m) { D[d][m] = T(0); G[d][m] = T(0); }
+      for (int m = 0; m < 8; ++m) D[d][m] = S(0);
       continue;
     }
     const int64_t o = P.off[d];
-    const T idx = T(1.0 / dxp[d]);
     for (int m = 0; m < 8; ++m) {
       if (m == 5 + d)
-        D[d][m] = u[(5 + d) * Nc + cell + o] - u[(5 + d) * Nc + cell];
+        D[d][m] = u(ub + (5 + d) * Nc + o) - u(ub + (5 + d) * Nc);
       else
-        D[d][m] = limited_slope(qc[m] - q[m * Nc + cell - o], q[m * Nc + cell + o] - qc[m], c.limiter);
-      G[d][m] = D[d][m] * idx;
+        D[d][m] = limited_slope(qc[m] - q(qb + m * Nc - o), q(qb + m * Nc + o) - qc[m], c.limiter);
     }
   }
-  T r[8];
-  prim_rate(qc, G, c.gamma, r);
-  const T hdt = T(0.5 * dt);
-  T* w = Wout + P.wbase;
-  const int64_t wc = wcell_of(P, g, i, j, k);
-  const int64_t Nw = P.Nwc;
-  for (int m = 0; m < 8; ++m) w[(W_QT + m) * Nw + wc] = qc[m] + hdt * r[m];
+  S r[8];
+  prim_rate(qc, D, ix, c.gamma, r);
+  const S hdt = S(0.5 * dt);
+  for (int m = 0; m < 8; ++m) w[W_QT + m] = qc[m] + hdt * r[m];
   for (int d = 0; d < 3; ++d)
     for (int m = 0; m < 8; ++m)
-      if (m != 5 + d) w[slope_slot(d, m) * Nw + wc] = D[d][m];
+      if (m != 5 + d) w[slope_slot(d, m)] = D[d][m];
   // half-step face field B^{n+1/2} = B^n + dt/2 curl E^n on the three lower faces
   for (int d = 0; d < 3; ++d) {
     const int a = (d + 1) % 3, b = (d + 2) % 3;
-    T v = u[(5 + d) * Nc + cell];
-    if (active(P, a)) v = v + T(0.5 * dt / dxp[a]) * (E[b * Nc + cell + P.off[a]] - E[b * Nc + cell]);
-    if (active(P, b)) v = v - T(0.5 * dt / dxp[b]) * (E[a * Nc + cell + P.off[b]] - E[a * Nc + cell]);
-    w[(W_BH + d) * Nw + wc] = v;
+    S v = u(ub + (5 + d) * Nc);
+    if (active(P, a)) v = v + S(0.5 * dt / dxp[a]) * (e(eb + b * Nc + P.off[a]) - e(eb + b * Nc));
+    if (active(P, b)) v = v - S(0.5 * dt / dxp[b]) * (e(eb + a * Nc + P.off[b]) - e(eb + a * Nc));
+    w[W_BH + d] = v;
   }
   // transverse slopes of the face fields (used by the corner states of the edges)
   for (int d = 0; d < 3; ++d) {
-    const T* B = u + (5 + d) * Nc;
-    for (int e = 0; e < 3; ++e) {
-      if (e == d) continue;
-      T s = T(0);
-      if (active(P, e)) {
-        const int64_t o = P.off[e];
-        s = limited_slope(B[cell] - B[cell - o], B[cell + o] - B[cell], c.limiter);
+    const int64_t B = ub + (5 + d) * Nc;
+    for (int f = 0; f < 3; ++f) {
+      if (f == d) continue;
+      S sl = S(0);
+      if (active(P, f)) {
+        const int64_t o = P.off[f];
+        sl = limited_slope(u(B) - u(B - o), u(B + o) - u(B), c.limiter);
       }
-      w[dbf_slot(d, e) * Nw + wc] = s;
+      w[dbf_slot(d, f)] = sl;
     }
   }
 }
 
 // ---------------------------------------------------- stage 4a: HLLD face flux
 // Face of direction d on the lower side of padded cell (i, j, k).  Returns the flux in
-// the face frame (rho, m_n, m_t1, m_t2, E) with (d, t1, t2) cyclic.
-template <typename T>
-__host__ __device__ __forceinline__ void face_flux_item(const PatchDev& P, int g, int d, int i, int j,
-                                                        int k, const T* Win, const Consts<T>& c,
-                                                        T F[5]) {
-  const T* w = Win + P.wbase;
+// the face frame (rho, m_n, m_t1, m_t2, E) with (d, t1, t2) cyclic.  w reads the predictor
+// data (absolute index P.wbase + v Nwc + wcell).
+template <typename S, class AW>
+__host__ __device__ __forceinline__ void face_point(const PatchDev& P, int g, int d, int i, int j,
+                                                    int k, const AW& w, const Consts<S>& c,
+                                                    S F[5]) {
   const int64_t Nw = P.Nwc;
-  const int64_t wr = wcell_of(P, g, i, j, k);
+  const int64_t wr = P.wbase + wcell_of(P, g, i, j, k);
   const int64_t wl = wr - P.woff[d];
   const int a = (d + 1) % 3, b = (d + 2) % 3;
   const int comp[7] = {0, 1 + d, 1 + a, 1 + b, 4, 5 + a, 5 + b};
-  T s[2][7];
+  S s[2][7];
   for (int t = 0; t < 7; ++t) {
     const int m = comp[t];
     const int sl = slope_slot(d, m);
-    s[0][t] = w[m * Nw + wl] + T(0.5) * w[sl * Nw + wl];
-    s[1][t] = w[m * Nw + wr] - T(0.5) * w[sl * Nw + wr];
+    s[0][t] = w(wl + m * Nw) + S(0.5) * w(wl + sl * Nw);
+    s[1][t] = w(wr + m * Nw) - S(0.5) * w(wr + sl * Nw);
   }
   for (int k2 = 0; k2 < 2; ++k2) {
     if (s[k2][0] < c.rho_floor) s[k2][0] = c.rho_floor;
     if (s[k2][4] < c.p_floor) s[k2][4] = c.p_floor;
   }
-  const T bn = w[(W_BH + d) * Nw + wr];
+  const S bn = w(wr + (W_BH + d) * Nw);
   hlld_flux(s, bn, c, F);
 }
 
-// predicted corner state of predictor cell wc at corner (sa, sb) for an edge along e:
-// (rho, u_a, u_b, p, B_e, B_a, B_b)
-template <typename T>
-__host__ __device__ __forceinline__ void corner_state(const PatchDev& P, const T* w, int64_t wc, int e,
-                                                      int sa, int sb, const Consts<T>& c, T C[7]) {
+// predicted corner state of predictor cell wc (absolute) at corner (sa, sb) for an edge
+// along e: (rho, u_a, u_b, p, B_e, B_a, B_b)
+template <typename S, class AW>
+__host__ __device__ __forceinline__ void corner_state(const PatchDev& P, const AW& w, int64_t wc,
+                                                      int e, int sa, int sb, const Consts<S>& c,
+                                                      S C[7]) {
   const int64_t Nw = P.Nwc;
   const int a = (e + 1) % 3, b = (e + 2) % 3;
   const int comp[5] = {0, 1 + a, 1 + b, 4, 5 + e};
   for (int t = 0; t < 5; ++t) {
     const int m = comp[t];
-    const T ha = T(0.5) * w[slope_slot(a, m) * Nw + wc];
-    const T hb = T(0.5) * w[slope_slot(b, m) * Nw + wc];
-    C[t] = w[m * Nw + wc] + ((sa > 0 ? ha : -ha) + (sb > 0 ? hb : -hb));
+    const S ha = S(0.5) * w(wc + slope_slot(a, m) * Nw);
+    const S hb = S(0.5) * w(wc + slope_slot(b, m) * Nw);
+    C[t] = w(wc + m * Nw) + ((sa > 0 ? ha : -ha) + (sb > 0 ? hb : -hb));
   }
   const int64_t fa = wc + (sa > 0 ? P.woff[a] : 0);
   const int64_t fb = wc + (sb > 0 ? P.woff[b] : 0);
-  const T ta = T(0.5) * w[dbf_slot(a, b) * Nw + fa];
-  const T tb = T(0.5) * w[dbf_slot(b, a) * Nw + fb];
-  C[5] = w[(W_BH + a) * Nw + fa] + (sb > 0 ? ta : -ta);
-  C[6] = w[(W_BH + b) * Nw + fb] + (sa > 0 ? tb : -tb);
+  const S ta = S(0.5) * w(fa + dbf_slot(a, b) * Nw);
+  const S tb = S(0.5) * w(fb + dbf_slot(b, a) * Nw);
+  C[5] = w(fa + (W_BH + a) * Nw) + (sb > 0 ? ta : -ta);
+  C[6] = w(fb + (W_BH + b) * Nw) + (sa > 0 ? tb : -tb);
   if (C[0] < c.rho_floor) C[0] = c.rho_floor;
   if (C[3] < c.p_floor) C[3] = c.p_floor;
 }
 
 // -------------------------------------------------------- stage 4b: edge EMF
 // Edge along e at the (a, b) = (-1/2, -1/2) corner of padded cell (i, j, k).
-template <typename T>
-__host__ __device__ __forceinline__ T edge_emf_item(const PatchDev& P, int g, int e, int i, int j, int k,
-                                                    const T* Win, const Consts<T>& c) {
-  const T* w = Win + P.wbase;
+template <typename S, class AW>
+__host__ __device__ __forceinline__ S edge_point(const PatchDev& P, int g, int e, int i, int j, int k,
+                                                 const AW& w, const Consts<S>& c) {
   const int a = (e + 1) % 3, b = (e + 2) % 3;
-  const int64_t wc = wcell_of(P, g, i, j, k);
+  const int64_t wc = P.wbase + wcell_of(P, g, i, j, k);
   const int64_t oa = P.woff[a], ob = P.woff[b];
-  T C[4][7];
+  S C[4][7];
   corner_state(P, w, wc - oa - ob, e, +1, +1, c, C[0]);  // SW
   corner_state(P, w, wc - ob, e, -1, +1, c, C[1]);       // SE
   corner_state(P, w, wc - oa, e, +1, -1, c, C[2]);       // NW
   corner_state(P, w, wc, e, -1, -1, c, C[3]);            // NE
   return uct_emf(C, c);
+}
+
+// ------------------------------------------------ forward writers of stages 1-3
+template <typename T>
+__host__ __device__ __forceinline__ int prim_item(const PatchDev& P, int64_t cell, const T* U, T* S,
+                                                  const Consts<T>& c) {
+  T q[8];
+  const int bad = prim_point(P, cell, Ld<T>{U}, c, q);
+  T* o = S + P.sbase + cell;
+  for (int m = 0; m < 8; ++m) o[m * P.Nc] = q[m];
+  return bad;
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void en_item(const PatchDev& P, int64_t cell, const T* U, T* S) {
+  T E[3];
+  en_point(P, cell, Ld<T>{S}, Ld<T>{U}, E);
+  T* o = S + P.sbase + 8 * P.Nc + cell;
+  for (int e = 0; e < 3; ++e) o[e * P.Nc] = E[e];
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void pred_item(const PatchDev& P, int g, int i, int j, int k,
+                                                   const T* U, const T* S, T* Wout, double dt,
+                                                   const double* dxp, const Consts<T>& c) {
+  T w[NW];
+  pred_point(P, i, j, k, Ld<T>{U}, Ld<T>{S}, Ld<T>{S}, dt, dxp, c, w);
+  T* o = Wout + P.wbase + wcell_of(P, g, i, j, k);
+  for (int v = 0; v < NW; ++v) o[v * P.Nwc] = w[v];
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void face_flux_item(const PatchDev& P, int g, int d, int i, int j,
+                                                        int k, const T* Win, const Consts<T>& c,
+                                                        T F[5]) {
+  face_point(P, g, d, i, j, k, Ld<T>{Win}, c, F);
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ T edge_emf_item(const PatchDev& P, int g, int e, int i, int j, int k,
+                                                    const T* Win, const Consts<T>& c) {
+  return edge_point(P, g, e, i, j, k, Ld<T>{Win}, c);
 }
 
 // -------------------------------------------------------------- time step
@@ -280,7 +331,7 @@ __host__ __device__ __forceinline__ double cfl_item(const PatchDev& P, int64_t c
   const T* u = U + P.ubase;
   T rho = u[cell];
   if (rho < c.rho_floor) rho = c.rho_floor;
-  const T ir = T(1) / rho;
+  const T ir = m_rcp(rho);
   const T v[3] = {u[Nc + cell] * ir, u[2 * Nc + cell] * ir, u[3 * Nc + cell] * ir};
   T B[3];
   for (int d = 0; d < 3; ++d) B[d] = T(0.5) * (u[(5 + d) * Nc + cell] + u[(5 + d) * Nc + cell + P.off[d]]);
@@ -297,12 +348,13 @@ __host__ __device__ __forceinline__ double cfl_item(const PatchDev& P, int64_t c
 }
 
 // ------------------------------------------------------------------ guard fill
-// Copies one guard element of patch p from its owner (neighbour table, 27 entries per
-// patch; -1 = domain boundary: zero-gradient copy).  Returns 0 if (i, j, k) is owned or
-// was filled, 1 if the table is inconsistent.
-template <typename T>
-__host__ __device__ __forceinline__ int guard_item(const PatchDev* PT, int p, int g, int i, int j,
-                                                   int k, T* U, const int32_t* nbr, int npatch) {
+// Owner of padded cell (i, j, k) of patch p under a 27-entry neighbour table (-1 = domain
+// boundary: zero-gradient copy of the nearest owned cell).  Returns 0 if the cell is owned
+// (src = p, scell = its own cell), 1 if it is a guard with owner (src, scell), -1 if the
+// table is inconsistent.
+__host__ __device__ __forceinline__ int guard_source(const PatchDev* PT, int p, int g, int i, int j,
+                                                     int k, const int32_t* nbr, int npatch, int& src,
+                                                     int64_t& scell) {
   const PatchDev& P = PT[p];
   int idx[3] = {i, j, k};
   int o[3] = {0, 0, 0};
@@ -313,7 +365,11 @@ __host__ __device__ __forceinline__ int guard_item(const PatchDev* PT, int p, in
     else if (idx[d] >= g + P.n[d]) o[d] = 1;
     guard |= o[d] != 0;
   }
-  if (!guard) return 0;
+  src = p;
+  if (!guard) {
+    scell = cell_of(P, i, j, k);
+    return 0;
+  }
   for (int d = 0; d < 3; ++d) {
     if (!o[d]) continue;
     int f[3] = {0, 0, 0};
@@ -323,21 +379,346 @@ __host__ __device__ __forceinline__ int guard_item(const PatchDev* PT, int p, in
       o[d] = 0;
     }
   }
-  int src = p;
   if (o[0] || o[1] || o[2]) src = nbr[27 * p + (o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1)];
-  if (src < 0 || src >= npatch) return 1;
+  if (src < 0 || src >= npatch) return -1;
   const PatchDev& Q = PT[src];
-  if (Q.n[0] != P.n[0] || Q.n[1] != P.n[1] || Q.n[2] != P.n[2]) return 1;
-  const int64_t cs = cell_of(Q, idx[0] - o[0] * P.n[0], idx[1] - o[1] * P.n[1], idx[2] - o[2] * P.n[2]);
+  if (Q.n[0] != P.n[0] || Q.n[1] != P.n[1] || Q.n[2] != P.n[2]) return -1;
+  scell = cell_of(Q, idx[0] - o[0] * P.n[0], idx[1] - o[1] * P.n[1], idx[2] - o[2] * P.n[2]);
+  return 1;
+}
+
+// Copies one guard cell of patch p (all 8 fields) from its owner.  Returns 0 if (i, j, k)
+// is owned or was filled, 1 if the table is inconsistent.
+template <typename T>
+__host__ __device__ __forceinline__ int guard_item(const PatchDev* PT, int p, int g, int i, int j,
+                                                   int k, T* U, const int32_t* nbr, int npatch) {
+  int src;
+  int64_t cs;
+  const int r = guard_source(PT, p, g, i, j, k, nbr, npatch, src, cs);
+  if (r == 0) return 0;
+  if (r < 0) return 1;
+  const PatchDev& P = PT[p];
+  const PatchDev& Q = PT[src];
   const int64_t cd = cell_of(P, i, j, k);
   for (int m = 0; m < 8; ++m) U[P.ubase + m * P.Nc + cd] = U[Q.ubase + m * Q.Nc + cs];
   return 0;
+}
+
+// ================================================================ adjoint stages
+// The adjoint of one update at fixed dt is assembled stage by stage in reverse order.  Each
+// adjoint element is a gather over the forward items that read the corresponding input:
+// lambda_x = sum over items I reading x of  sum_o lambda_o(I) d o(I) / d x, where the
+// derivative is the forward item evaluated in dual numbers with x seeded.  Every sum runs in a
+// fixed order, so the result is deterministic; no atomics.
+
+__host__ __device__ __forceinline__ bool owned(const PatchDev& P, int g, const int x[3]) {
+  for (int d = 0; d < 3; ++d)
+    if (active(P, d) && (x[d] < g || x[d] >= g + P.n[d])) return false;
+  return true;
+}
+
+// adjoint of the update outputs: owned cells and faces only
+template <typename T>
+__host__ __device__ __forceinline__ T lam_out_at(const PatchDev& P, int g, const T* lam, int m,
+                                                 const int x[3]) {
+  if (!owned(P, g, x)) return T(0);
+  return lam[P.ubase + m * P.Nc + cell_of(P, x[0], x[1], x[2])];
+}
+
+// forward face set of direction d: normal index in [g, g+n], transverse in [g, g+n)
+__host__ __device__ __forceinline__ bool face_computed(const PatchDev& P, int g, int d, const int x[3]) {
+  for (int f = 0; f < 3; ++f) {
+    if (!active(P, f)) continue;
+    const int hi = g + P.n[f] + (f == d ? 1 : 0);
+    if (x[f] < g || x[f] >= hi) return false;
+  }
+  return true;
+}
+
+// forward edge set of direction e: transverse indices in [g, g+n], along e in [g, g+n)
+__host__ __device__ __forceinline__ bool edge_computed(const PatchDev& P, int g, int e, const int x[3]) {
+  for (int f = 0; f < 3; ++f) {
+    if (!active(P, f)) continue;
+    const int hi = g + P.n[f] + (f != e ? 1 : 0);
+    if (x[f] < g || x[f] >= hi) return false;
+  }
+  return true;
+}
+
+__host__ __device__ __forceinline__ bool in_box(const PatchDev& P, int kind, int g, const int x[3]) {
+  int lo[3], sz[3];
+  box_of(P, kind, g, lo, sz);
+  for (int d = 0; d < 3; ++d)
+    if (x[d] < lo[d] || x[d] >= lo[d] + sz[d]) return false;
+  return true;
+}
+
+// lambda of the face flux component m (global frame) of direction d at face x
+template <typename T>
+__host__ __device__ __forceinline__ T lam_flux(const PatchDev& P, int g, const T* lam, int d, int m,
+                                               const int x[3], T dtdx) {
+  int y[3] = {x[0], x[1], x[2]};
+  y[d] -= 1;
+  return dtdx * (lam_out_at(P, g, lam, m, x) - lam_out_at(P, g, lam, m, y));
+}
+
+// lambda of the edge EMF along e at edge x (constrained-transport update, per-direction dx)
+template <typename T>
+__host__ __device__ __forceinline__ T lam_emf(const PatchDev& P, int g, const T* lam, int e,
+                                              const int x[3], const T dtdx[3]) {
+  T r = T(0);
+  const int d1 = (e + 1) % 3, a1 = (e + 2) % 3;  // B_d1 += dtdx_a1 (E_e[c + a1] - E_e[c])
+  if (active(P, a1)) {
+    int y[3] = {x[0], x[1], x[2]};
+    y[a1] -= 1;
+    r = r + dtdx[a1] * (lam_out_at(P, g, lam, 5 + d1, y) - lam_out_at(P, g, lam, 5 + d1, x));
+  }
+  const int d2 = (e + 2) % 3, b2 = (e + 1) % 3;  // B_d2 -= dtdx_b2 (E_e[c + b2] - E_e[c])
+  if (active(P, b2)) {
+    int y[3] = {x[0], x[1], x[2]};
+    y[b2] -= 1;
+    r = r + dtdx[b2] * (lam_out_at(P, g, lam, 5 + d2, x) - lam_out_at(P, g, lam, 5 + d2, y));
+  }
+  return r;
+}
+
+// lambda_W[v] at predictor cell x: faces and edges that read it
+template <typename T>
+__host__ __device__ __forceinline__ T adj_w_item(const PatchDev& P, int g, const int x[3], int v,
+                                                 const T* W, const T* lam, double dt,
+                                                 const double* dxp, const Consts<T>& c) {
+  typedef Dual<T> S;
+  const Consts<S> cd = lift<S>(c);
+  const LdSeed<T> acc{W, P.wbase + (int64_t)v * P.Nwc + wcell_of(P, g, x[0], x[1], x[2])};
+  const T dtdx[3] = {T(dt / dxp[0]), T(dt / dxp[1]), T(dt / dxp[2])};
+  T sum = T(0);
+  for (int d = 0; d < 3; ++d) {
+    if (!active(P, d)) continue;
+    const int a = (d + 1) % 3, b = (d + 2) % 3;
+    const int map[5] = {0, 1 + d, 1 + a, 1 + b, 4};
+    for (int s = 0; s < 2; ++s) {
+      int f[3] = {x[0], x[1], x[2]};
+      f[d] += s;
+      if (!face_computed(P, g, d, f)) continue;
+      S F[5];
+      face_point(P, g, d, f[0], f[1], f[2], acc, cd, F);
+      for (int t = 0; t < 5; ++t) sum = sum + lam_flux(P, g, lam, d, map[t], f, dtdx[d]) * F[t].d;
+    }
+  }
+  for (int e = 0; e < 3; ++e) {
+    const int a = (e + 1) % 3, b = (e + 2) % 3;
+    for (int sb = 0; sb <= (active(P, b) ? 1 : 0); ++sb)
+      for (int sa = 0; sa <= (active(P, a) ? 1 : 0); ++sa) {
+        int y[3] = {x[0], x[1], x[2]};
+        y[a] += sa;
+        y[b] += sb;
+        if (!edge_computed(P, g, e, y)) continue;
+        const S em = edge_point(P, g, e, y[0], y[1], y[2], acc, cd);
+        sum = sum + lam_emf(P, g, lam, e, y, dtdx) * em.d;
+      }
+  }
+  return sum;
+}
+
+// sum over the predictor cells y within one cell of x (active directions) of
+// lambda_W(y) . dW(y)/d(seeded input), the seed given by the accessors
+template <typename T, class AU, class AQ, class AE>
+__host__ __device__ __forceinline__ T pred_gather(const PatchDev& P, int g, const int x[3],
+                                                  const AU& u, const AQ& q, const AE& e,
+                                                  const T* LW, double dt, const double* dxp,
+                                                  const Consts<Dual<T>>& cd) {
+  T sum = T(0);
+  const int r0 = active(P, 0), r1 = active(P, 1), r2 = active(P, 2);
+  for (int dz = -r2; dz <= r2; ++dz)
+    for (int dy = -r1; dy <= r1; ++dy)
+      for (int dx = -r0; dx <= r0; ++dx) {
+        const int y[3] = {x[0] + dx, x[1] + dy, x[2] + dz};
+        if (!in_box(P, BOX_PRED, g, y)) continue;
+        Dual<T> w[NW];
+        pred_point(P, y[0], y[1], y[2], u, q, e, dt, dxp, cd, w);
+        const T* lw = LW + P.wbase + wcell_of(P, g, y[0], y[1], y[2]);
+        for (int v = 0; v < NW; ++v) sum = sum + lw[(int64_t)v * P.Nwc] * w[v].d;
+      }
+  return sum;
+}
+
+// sum over the edge-EMF cells y within one cell of x of lambda_E(y) . dE(y)/d(seed)
+template <typename T, class AQ, class AU>
+__host__ __device__ __forceinline__ T en_gather(const PatchDev& P, int g, const int x[3], const AQ& q,
+                                                const AU& u, const T* LS) {
+  T sum = T(0);
+  const int r0 = active(P, 0), r1 = active(P, 1), r2 = active(P, 2);
+  for (int dz = -r2; dz <= r2; ++dz)
+    for (int dy = -r1; dy <= r1; ++dy)
+      for (int dx = -r0; dx <= r0; ++dx) {
+        const int y[3] = {x[0] + dx, x[1] + dy, x[2] + dz};
+        if (!in_box(P, BOX_EN, g, y)) continue;
+        Dual<T> E[3];
+        const int64_t cy = cell_of(P, y[0], y[1], y[2]);
+        en_point(P, cy, q, u, E);
+        const T* le = LS + P.sbase + 8 * P.Nc + cy;
+        for (int k = 0; k < 3; ++k) sum = sum + le[k * P.Nc] * E[k].d;
+      }
+  return sum;
+}
+
+// lambda_E[k] at edge-EMF cell x (only the predictor reads E)
+template <typename T>
+__host__ __device__ __forceinline__ T adj_e_item(const PatchDev& P, int g, const int x[3], int k,
+                                                 const T* U, const T* S, const T* LW, double dt,
+                                                 const double* dxp, const Consts<T>& c) {
+  const Consts<Dual<T>> cd = lift<Dual<T>>(c);
+  const int64_t seed = P.sbase + 8 * P.Nc + (int64_t)k * P.Nc + cell_of(P, x[0], x[1], x[2]);
+  return pred_gather(P, g, x, LdSeed<T>{U, -1}, LdSeed<T>{S, -1}, LdSeed<T>{S, seed}, LW, dt, dxp, cd);
+}
+
+// lambda_Q[m] at primitive cell x (read by the predictor and the edge EMFs at time n)
+template <typename T>
+__host__ __device__ __forceinline__ T adj_q_item(const PatchDev& P, int g, const int x[3], int m,
+                                                 const T* U, const T* S, const T* LW, const T* LS,
+                                                 double dt, const double* dxp, const Consts<T>& c) {
+  const Consts<Dual<T>> cd = lift<Dual<T>>(c);
+  const int64_t seed = P.sbase + (int64_t)m * P.Nc + cell_of(P, x[0], x[1], x[2]);
+  const LdSeed<T> qs{S, seed}, plainU{U, -1}, plainS{S, -1};
+  T sum = pred_gather(P, g, x, plainU, qs, plainS, LW, dt, dxp, cd);
+  if (m >= 1 && m <= 3) sum = sum + en_gather(P, g, x, qs, plainU, LS);
+  return sum;
+}
+
+// lambda_U[m] at padded cell x: direct term of the update, predictor (face fields), edge EMFs
+// at time n (face fields) and primitives
+template <typename T>
+__host__ __device__ __forceinline__ T adj_u_item(const PatchDev& P, int g, const int x[3], int m,
+                                                 const T* U, const T* S, const T* LW, const T* LS,
+                                                 const T* lam, double dt, const double* dxp,
+                                                 const Consts<T>& c) {
+  const Consts<Dual<T>> cd = lift<Dual<T>>(c);
+  const int64_t seed = P.ubase + (int64_t)m * P.Nc + cell_of(P, x[0], x[1], x[2]);
+  const LdSeed<T> us{U, seed}, plainS{S, -1};
+  T sum = lam_out_at(P, g, lam, m, x);
+  if (m >= 5) {
+    sum = sum + pred_gather(P, g, x, us, plainS, plainS, LW, dt, dxp, cd);
+    sum = sum + en_gather(P, g, x, plainS, us, LS);
+  }
+  // primitives of x and of the cell below in direction m-5 (cell-centred field average)
+  const int r0 = active(P, 0), r1 = active(P, 1), r2 = active(P, 2);
+  for (int dz = -r2; dz <= 0; ++dz)
+    for (int dy = -r1; dy <= 0; ++dy)
+      for (int dx = -r0; dx <= 0; ++dx) {
+        const int y[3] = {x[0] + dx, x[1] + dy, x[2] + dz};
+        if (!in_box(P, BOX_PRIM, g, y)) continue;
+        Dual<T> q[8];
+        const int64_t cy = cell_of(P, y[0], y[1], y[2]);
+        prim_point(P, cy, us, cd, q);
+        const T* lq = LS + P.sbase + cy;
+        for (int k = 0; k < 8; ++k) sum = sum + lq[k * P.Nc] * q[k].d;
+      }
+  return sum;
+}
+
+// ------------------------------------------------ fused predictor tile (stages 1-3)
+// One tile of the predictor box [g-1, g+n+1): primitives and face fields of the tile plus one
+// cell around it go to shared memory L, then the edge EMFs at time n of the tile's cells and
+// the layer above, then the 38 predictor values of the tile's cells -> W.  Stages 1-3 read
+// shared memory through a patch description F of the local box (Q fields at [0, 8 Nl), E at
+// [8 Nl, 11 Nl), face fields at [11 Nl, 14 Nl) with F.ubase = 6 Nl), so the point functions
+// are the ones of the staged kernels.  Returns 1 if a non-physical state was met.
+template <int PX, int PY, int PZ>
+struct PredShape {
+  static constexpr int LX = PX > 1 ? PX + 2 : 1, LY = PY > 1 ? PY + 2 : 1, LZ = PZ > 1 ? PZ + 2 : 1;
+  static constexpr int NL = LX * LY * LZ;
+  static constexpr int LDS_ELEMS = 14 * NL;
+  static constexpr int THREADS = PX * PY * PZ < 64 ? 64 : PX * PY * PZ;
+};
+
+template <typename T, int PX, int PY, int PZ, class X>
+__host__ __device__ __forceinline__ int predict_tile(X& ex, T* L, const PatchDev& P, int g,
+                                                     const TileDev& tl, const T* U, T* W,
+                                                     double dt, const double* dxp,
+                                                     const Consts<T>& c) {
+  const int PT[3] = {PX, PY, PZ}, t0[3] = {tl.x0, tl.y0, tl.z0};
+  int e3[3], o3[3], l3[3];  // tile extent, padded index of its first cell, local box extent
+  for (int d = 0; d < 3; ++d) {
+    if (active(P, d)) {
+      e3[d] = P.n[d] + 2 - t0[d] < PT[d] ? P.n[d] + 2 - t0[d] : PT[d];
+      o3[d] = g - 1 + t0[d];
+      l3[d] = e3[d] + 2;
+    } else {
+      e3[d] = 1;
+      o3[d] = 0;
+      l3[d] = 1;
+    }
+  }
+  PatchDev F = {};
+  F.act = P.act;
+  for (int d = 0; d < 3; ++d) F.N[d] = l3[d];
+  F.Nc = (int64_t)l3[0] * l3[1] * l3[2];
+  F.off[0] = active(P, 0) ? 1 : 0;
+  F.off[1] = active(P, 1) ? l3[0] : 0;
+  F.off[2] = active(P, 2) ? (int64_t)l3[0] * l3[1] : 0;
+  F.sbase = 0;
+  F.ubase = 6 * F.Nc;
+  const int64_t Nl = F.Nc;
+  const int tid = ex.tid(), nth = ex.nthr();
+  int bad = 0;
+  // 1. primitives and face fields of the local box (local index 0 = one cell below the tile)
+  for (int it = tid; it < Nl; it += nth) {
+    const int li = it % l3[0], lj = (it / l3[0]) % l3[1], lk = it / (l3[0] * l3[1]);
+    const int gi = active(P, 0) ? o3[0] - 1 + li : 0;
+    const int gj = active(P, 1) ? o3[1] - 1 + lj : 0;
+    const int gk = active(P, 2) ? o3[2] - 1 + lk : 0;
+    const int64_t gc = cell_of(P, gi, gj, gk);
+    T q[8];
+    bad |= prim_point(P, gc, Ld<T>{U}, c, q);
+    for (int m = 0; m < 8; ++m) L[m * Nl + it] = q[m];
+    for (int d = 0; d < 3; ++d) L[(11 + d) * Nl + it] = U[P.ubase + (5 + d) * P.Nc + gc];
+  }
+  ex.sync();
+  // 2. edge EMFs at time n on local cells [1, l) of the active directions
+  int m3[3], lo3[3];
+  for (int d = 0; d < 3; ++d) {
+    m3[d] = active(P, d) ? l3[d] - 1 : 1;
+    lo3[d] = active(P, d) ? 1 : 0;
+  }
+  const int ne = m3[0] * m3[1] * m3[2];
+  for (int it = tid; it < ne; it += nth) {
+    const int li = lo3[0] + it % m3[0], lj = lo3[1] + (it / m3[0]) % m3[1],
+              lk = lo3[2] + it / (m3[0] * m3[1]);
+    const int64_t lc = cell_of(F, li, lj, lk);
+    T E[3];
+    en_point(F, lc, Ld<T>{L}, Ld<T>{L}, E);
+    for (int e = 0; e < 3; ++e) L[(8 + e) * Nl + lc] = E[e];
+  }
+  ex.sync();
+  // 3. predictor values of the tile's cells
+  const int nt = e3[0] * e3[1] * e3[2];
+  for (int it = tid; it < nt; it += nth) {
+    const int ti = it % e3[0], tj = (it / e3[0]) % e3[1], tk = it / (e3[0] * e3[1]);
+    T w[NW];
+    pred_point(F, lo3[0] + ti, lo3[1] + tj, lo3[2] + tk, Ld<T>{L}, Ld<T>{L}, Ld<T>{L}, dt, dxp, c,
+               w);
+    const int gi = active(P, 0) ? o3[0] + ti : 0;
+    const int gj = active(P, 1) ? o3[1] + tj : 0;
+    const int gk = active(P, 2) ? o3[2] + tk : 0;
+    T* o = W + P.wbase + wcell_of(P, g, gi, gj, gk);
+    for (int v = 0; v < NW; ++v) o[v * P.Nwc] = w[v];
+  }
+  return bad;
 }
 
 // ---------------------------------------------------- solver tile (fluxes + update)
 // One tile of TX x TY x TZ interior cells: HLLD fluxes on its faces, edge EMFs on its
 // edges (shared memory), then the conservative + constrained-transport update of its
 // cells.  X provides tid(), nthr() and sync() of the work-group.
+// value of lane 0 of the wavefront (the caller guarantees it is the same on every lane)
+__host__ __device__ __forceinline__ int wave_uniform(int v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_readfirstlane(v);
+#else
+  return v;
+#endif
+}
+
 template <int TX, int TY, int TZ>
 struct TileShape {
   static constexpr int NFX = (TX + 1) * TY * TZ, NFY = TX * (TY + 1) * TZ, NFZ = TX * TY * (TZ + 1);
@@ -345,6 +726,7 @@ struct TileShape {
                        NEY = (TX + 1) * TY * (TZ + 1);
   static constexpr int LDS_ELEMS = 5 * (NFX + NFY + NFZ) + NEZ + NEX + NEY;
   static constexpr int THREADS = TX * TY * TZ < 64 ? 64 : TX * TY * TZ;
+  static_assert(THREADS % 64 == 0, "solver work-groups are whole wavefronts");
 };
 
 template <typename T, int TX, int TY, int TZ, class X>
@@ -367,17 +749,34 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
   const int i0 = ax ? g + tl.x0 : 0, j0 = ay ? g + tl.y0 : 0, k0 = az ? g + tl.z0 : 0;
   const int tid = ex.tid(), nth = ex.nthr();
 
-  // faces: local extents (t + 1 along the face normal)
+  // Work list of the tile: six segments (faces normal to x, y, z; edges along x, y, z),
+  // each padded to whole wavefronts.  The work-group size is a multiple of the wavefront,
+  // so every wavefront works on one segment per round: the face/edge branch and the
+  // direction-dependent offsets stay uniform across its lanes, and the rounds are shared
+  // by all segments instead of each direction leaving a ragged last round.
+  constexpr int WAVE = 64;
+  int cnt[6], beg[7];
+  beg[0] = 0;
   for (int d = 0; d < 3; ++d) {
-    if (!active(P, d)) continue;
-    const int ex_[3] = {tx + (d == 0), ty + (d == 1), tz + (d == 2)};
-    const int LX = TX + (d == 0), LY = TY + (d == 1);
-    T* fd = d == 0 ? fx : (d == 1 ? fy : fz);
-    const int NF = d == 0 ? SH::NFX : (d == 1 ? SH::NFY : SH::NFZ);
-    const int nitem = ex_[0] * ex_[1] * ex_[2];
-    const int a = (d + 1) % 3, b = (d + 2) % 3;
-    for (int it = tid; it < nitem; it += nth) {
-      const int lx = it % ex_[0], ly = (it / ex_[0]) % ex_[1], lz = it / (ex_[0] * ex_[1]);
+    cnt[d] = active(P, d) ? (tx + (d == 0)) * (ty + (d == 1)) * (tz + (d == 2)) : 0;
+    cnt[3 + d] = (tx + (d != 0 && ax)) * (ty + (d != 1 && ay)) * (tz + (d != 2 && az));
+  }
+  for (int k = 0; k < 6; ++k) beg[k + 1] = beg[k] + (cnt[k] + WAVE - 1) / WAVE * WAVE;
+  for (int it = tid; it < beg[6]; it += nth) {
+    int k = 0;
+    while (k < 5 && it >= beg[k + 1]) ++k;
+    k = wave_uniform(k);
+    const int r = it - beg[k];
+    if (r >= cnt[k]) continue;
+    if (k < 3) {
+      // face normal to d: local extents t + 1 along d
+      const int d = k;
+      const int e0 = tx + (d == 0), e1 = ty + (d == 1);
+      const int lx = r % e0, ly = (r / e0) % e1, lz = r / (e0 * e1);
+      const int LX = TX + (d == 0), LY = TY + (d == 1);
+      T* fd = d == 0 ? fx : (d == 1 ? fy : fz);
+      const int NF = d == 0 ? SH::NFX : (d == 1 ? SH::NFY : SH::NFZ);
+      const int a = (d + 1) % 3, b = (d + 2) % 3;
       T F[5];
       face_flux_item(P, g, d, i0 + lx, j0 + ly, k0 + lz, Win, c, F);
       const int li = lx + LX * (ly + LY * lz);
@@ -386,16 +785,13 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
       fd[(1 + a) * NF + li] = F[2];
       fd[(1 + b) * NF + li] = F[3];
       fd[4 * NF + li] = F[4];
-    }
-  }
-  // edges: extents t + 1 along the two transverse directions when active
-  for (int e = 0; e < 3; ++e) {
-    const int ex_[3] = {tx + (e != 0 && ax), ty + (e != 1 && ay), tz + (e != 2 && az)};
-    const int LX = TX + (e != 0), LY = TY + (e != 1);
-    T* ed = e == 0 ? exx : (e == 1 ? ey : ez);
-    const int nitem = ex_[0] * ex_[1] * ex_[2];
-    for (int it = tid; it < nitem; it += nth) {
-      const int lx = it % ex_[0], ly = (it / ex_[0]) % ex_[1], lz = it / (ex_[0] * ex_[1]);
+    } else {
+      // edge along e: extents t + 1 along the two transverse directions when active
+      const int e = k - 3;
+      const int e0 = tx + (e != 0 && ax), e1 = ty + (e != 1 && ay);
+      const int lx = r % e0, ly = (r / e0) % e1, lz = r / (e0 * e1);
+      const int LX = TX + (e != 0), LY = TY + (e != 1);
+      T* ed = e == 0 ? exx : (e == 1 ? ey : ez);
       ed[lx + LX * (ly + LY * lz)] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
     }
   }

@@ -1,0 +1,168 @@
+"""Batched dispatch on the GPU: every launch configuration (solver tile shape x launch mode,
+staged or fused predictor) gives the same bits, the autotuner keeps a valid one, and a multi-step run captured in one
+HIP graph (per-patch local dt, or guard exchange + global dt) reproduces the eager calls
+bitwise on every replay and the oracle's run step for step."""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, log, make_bunch, rel_err_fields
+from paper_2508_09568_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _ragged(seed_noise=0):
+    w = W.uneven(mix=((9, 3), (13, 2), (20, 2)), nsteps=4)
+    return w.layout, w.U.numpy().copy(), np.ascontiguousarray(w.dx), w.gamma
+
+
+@pytest.mark.parametrize("case", ["ragged3d", "ot64", "sod"])
+def test_every_launch_configuration_gives_identical_bits(case):
+    import oracle
+    log(f"[gpu] launch configurations case={case}")
+    if case == "ragged3d":
+        L, U, dx, gam = _ragged()
+    elif case == "ot64":
+        w = W.orszag_tang(64, 32)
+        L, U, dx, gam = w.layout, w.U.copy(), w.dx, w.gamma
+        oracle.fill_guards(U, L.dims, L.g, w.nbr)
+    else:
+        w = W.sod(128, patches=2)
+        L, U, dx, gam = w.layout, w.U.copy(), w.dx, w.gamma
+        oracle.fill_guards(U, L.dims, L.g, w.nbr)
+    prm = oracle.Params(gamma=gam)
+    dt = oracle.cfl_many(U, L.dims, L.g, dx, prm)
+    ref = oracle.step_many(U, L.dims, L.g, dt, dx, prm)
+    B = make_bunch(L, gam)
+    cfgs = B.tile_configs()
+    assert len(cfgs) >= 2 and B.tile() == 0
+    Ui, dtd, dxd = dev(U), dev(dt), dev(dx)
+    outs = []
+    for fused in (0, 1):
+        B.set_predictor(fused)
+        assert B.predictor() == fused
+        for i, cfg in enumerate(cfgs):
+            B.set_tile(i)
+            Uo = dev(np.zeros_like(U))
+            B.update(Ui, Uo, dtd, dxd)
+            assert B.check() == 0
+            outs.append(host(Uo))
+            log(f"    predictor {fused} config {i} {cfg}: max|diff| vs first = "
+                f"{np.abs(outs[-1] - outs[0]).max():.3e}")
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    err = rel_err_fields(L, outs[0], ref)
+    assert err.max() <= 1e-12, err
+
+
+def test_autotune_picks_a_configuration_and_keeps_results():
+    log("[gpu] autotune on a ragged bunch")
+    L, U, dx, gam = _ragged()
+    import oracle
+    dt = oracle.cfl_many(U, L.dims, L.g, dx, oracle.Params(gamma=gam))
+    B = make_bunch(L, gam, precision=4)
+    Ui, dtd, dxd = dev(U).float(), dev(dt), dev(dx)
+    Uo = B.new_state()
+    B.update(Ui, Uo, dtd, dxd)
+    ref = host(Uo)
+    best, ms = B.autotune(Ui, Uo, dtd, dxd, reps=2)
+    log(f"    best {best} {B.tile_configs()[best]} ms {['%.3f' % m for m in ms]}")
+    assert 0 <= best < len(ms) and B.tile() == best
+    assert all(m > 0 for m in ms) and ms[best] == min(ms)
+    assert B.predictor() in (0, 1)
+    Uo.zero_()
+    B.update(Ui, Uo, dtd, dxd)
+    assert np.array_equal(host(Uo), ref)
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_graph_local_dt_run_matches_eager_calls_on_every_replay(precision):
+    """4 steps, each patch at its own CFL step, frozen guards, ping-pong buffers."""
+    import torch
+    log(f"[gpu] graph-captured local-dt run, precision {precision}")
+    L, U, dx, gam = _ragged()
+    B = make_bunch(L, gam, precision=precision)
+    dt_ = torch.float64 if precision == 8 else torch.float32
+    U0 = dev(U).to(dt_)
+    dxd = dev(dx)
+    # eager reference
+    a, b = U0.clone(), U0.clone()
+    dte = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    dts = []
+    for k in range(4):
+        B.cfl(a, dxd, dte, global_min=False)
+        dts.append(host(dte).copy())
+        B.update(a, b, dte, dxd)
+        a, b = b, a
+    eager = host(a)
+    # graph: U_a holds the input, result of an even step count lands in U_a
+    Ua, Ub = U0.clone(), U0.clone()
+    dtg = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    B.graph_capture(4, Ua, Ub, dtg, dxd, nbr=None, dt_mode=1)
+    for rep in range(3):
+        Ua.copy_(U0)
+        Ub.copy_(U0)
+        torch.cuda.synchronize()
+        B.graph_launch()
+        torch.cuda.synchronize()
+        got = host(Ua)
+        log(f"    replay {rep}: max|graph - eager| = {np.abs(got - eager).max():.3e}")
+        assert np.array_equal(got, eager)
+        assert np.array_equal(host(dtg), dts[-1])
+        assert B.check() == 0
+        # unrelated eager work between replays
+        (U0 * 2).sum().item()
+    if precision == 8:
+        import oracle
+        prm = oracle.Params(gamma=gam)
+        Uo = U.copy()
+        for k in range(4):
+            d = oracle.cfl_many(Uo, L.dims, L.g, dx, prm)
+            assert np.allclose(d, dts[k], rtol=1e-13, atol=0)
+            Uo = oracle.step_many(Uo, L.dims, L.g, dts[k], dx, prm)
+        err = rel_err_fields(L, eager, Uo)
+        log(f"    4 local-dt steps vs oracle: {err.max():.2e}")
+        assert err.max() <= 1e-11
+
+
+def test_graph_with_guard_exchange_and_global_dt_matches_eager_calls():
+    import torch
+    log("[gpu] graph-captured run with guard fill and global dt (OT 64^2)")
+    w = W.orszag_tang(64, 32)
+    L = w.layout
+    B = make_bunch(L, w.gamma)
+    U0 = dev(w.U)
+    dxd = dev(w.dx)
+    nb = dev(w.nbr.astype(np.int32))
+    a, b = U0.clone(), U0.clone()
+    dte = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    for k in range(5):
+        B.fill_guards(a, nb)
+        B.cfl(a, dxd, dte, global_min=True)
+        B.update(a, b, dte, dxd)
+        a, b = b, a
+    eager = host(a)     # odd step count: result in the second buffer of the pair
+    Ua, Ub = U0.clone(), U0.clone()
+    dtg = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    B.graph_capture(5, Ua, Ub, dtg, dxd, nbr=nb, dt_mode=2)
+    for rep in range(2):
+        Ua.copy_(U0)
+        Ub.copy_(U0)
+        B.graph_launch()
+        got = host(Ub)
+        assert np.array_equal(got, eager), rep
+    assert B.check() == 0
+
+
+def test_graph_capture_rejects_bad_arguments():
+    import torch
+
+    from paper_2508_09568_amd.binding import MhdError
+    L, U, dx, gam = _ragged()
+    B = make_bunch(L, gam)
+    Ua = dev(U)
+    dtg = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    with pytest.raises(MhdError):
+        B.graph_capture(2, Ua, Ua, dtg, dev(dx), dt_mode=1)
+    with pytest.raises(MhdError):
+        B.graph_launch()

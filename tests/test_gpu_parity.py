@@ -239,13 +239,15 @@ def test_chunked_scratch_gives_identical_results():
     assert np.array_equal(outs[0], outs[1])
 
 
-def test_nonphysical_state_is_reported():
-    log("[gpu] non-physical flag")
+@pytest.mark.parametrize("fused", [0, 1])
+def test_nonphysical_state_is_reported(fused):
+    log(f"[gpu] non-physical flag, predictor {fused}")
     L, U, dx, nbr, gam = _case("ot64")
     U = U.copy()
     V = L.view(U, 1)
     V[4, 0, 10, 10] = -1.0                     # negative total energy -> p < 0
     B = make_bunch(L, gam)
+    B.set_predictor(fused)
     Uo = dev(np.zeros_like(U))
     B.update(dev(U), Uo, dev(np.full(L.P, 1e-4)), dev(dx))
     from paper_2508_09568_amd.binding import MHD_ENONPHYS
