@@ -33,12 +33,41 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# HBM bytes of one FP64 update (every update kernel), measured with rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE on the turbulence workload and scaled by the same counters on a plain
+# 1 GiB device copy (FETCH_SIZE reads 0.5x there, WRITE_SIZE 1x); see profiles/.  Valid only
+# for the kernel sources it was measured on: reported as null once they change.
+MEASURED_TRAFFIC = {
+    "sources_sha256": None,
+    "bytes_per_update": None,
+    "profile": None,
+}
+
+
+def kernel_sources_sha256():
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in ("mhd_bunch.hip", "mhd_stages.hpp", "mhd_physics.hpp"):
+        with open(os.path.join(here, "paper_2508_09568_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(tile, fused):
+    m = MEASURED_TRAFFIC
+    if m["sources_sha256"] != kernel_sources_sha256() or m.get("tile") != list(tile) or \
+            m.get("fused_predictor") != fused:
+        return None
+    return m["bytes_per_update"]
+
+
 def algorithmic_bytes_per_cell(n, g, s):
     """Read every padded cell once, write every interior cell once, 8 fields."""
     return 8.0 * s * (((n + 2 * g) / n) ** 3 + 1.0)
 
 
-def run_precision(w, precision, steps, warmup, flops_per_cell, tile=None):
+def run_precision(w, precision, steps, warmup, flops_per_cell, tile=None, predictor=None):
     import numpy as np
     import torch
 
@@ -69,6 +98,8 @@ def run_precision(w, precision, steps, warmup, flops_per_cell, tile=None):
     else:                         # fixed configuration (profiling runs)
         best, tune_ms = tile, [float("nan")] * len(cfgs)
         B.set_tile(tile)
+    if predictor is not None:
+        B.set_predictor(predictor)
     for _ in range(warmup):
         step(Ua, Ub)
         Ua, Ub = Ub, Ua
@@ -111,7 +142,8 @@ def run_precision(w, precision, steps, warmup, flops_per_cell, tile=None):
         "bytes_per_cell": bpc,
         "update_tflops": flops_per_cell * cells / (upd_ms * 1e-3) / 1e12,
         "update_hbm_gbs": bpc * cells / (upd_ms * 1e-3) / 1e9,
-        "tile": {"chosen": list(cfgs[best]),
+        "tile": {"chosen": list(cfgs[best]), "fused_predictor": B.predictor(),
+                 "solver_split": B.solver_split(),
                  "tuned_ms": {str(list(c)): (None if m != m else round(m, 3))
                               for c, m in zip(cfgs, tune_ms)}},
         "state_host": Ua,
@@ -164,6 +196,8 @@ def run_batched(steps, steps_per_patch):
         raise RuntimeError("device status after the batched run")
     res_a = (Ua if steps % 2 == 0 else Ub).clone()
     cfg = B.tile_configs()[best]
+    fused = B.predictor()
+    split = B.solver_split()
     del B, Ua, Ub
     torch.cuda.empty_cache()
     log(f"[bench] (A) batched graph: {ms_a / steps:.2f} ms/step, tile {cfg}")
@@ -174,6 +208,8 @@ def run_batched(steps, steps_per_patch):
             idx = np.asarray(idx)
             Bs = Bunch(L.dims[idx], g=L.g, precision=4, gamma=w.gamma, cfl=w.cfl)
             Bs.set_tile(best if best < len(Bs.tile_configs()) else 0)
+            Bs.set_predictor(fused)
+            Bs.set_solver_split(split)
             seg = [U0[int(L.base[p]):int(L.base[p + 1])] for p in idx]
             ua = torch.cat(seg)
             subs.append((idx, Bs, ua, ua.clone(), dx[torch.as_tensor(idx).cuda()].contiguous(),
@@ -247,7 +283,7 @@ def run_batched(steps, steps_per_patch):
         "batched_graph": {"value": cells * steps / (ms_a * 1e-3), "ms_per_step": ms_a / steps,
                           "launch": "one HIP graph launch for all steps (CFL + update "
                                     "kernels of the whole bunch per step)",
-                          "tile": list(cfg)},
+                          "tile": list(cfg), "fused_predictor": fused},
         "per_bunch": {"value": cells * steps / (ms_b * 1e-3), "ms_per_step": ms_b / steps,
                       "bunches": len(groups), "launch": "same-size bunches of <= 300 patches",
                       "max_abs_diff_vs_batched": diff_b},
@@ -303,6 +339,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--tile", type=int, default=None,
                     help="use this launch configuration instead of autotuning")
+    ap.add_argument("--predictor", type=int, default=None, choices=(0, 1),
+                    help="force the staged (0) or fused (1) predictor")
+    ap.add_argument("--fp32-only", action="store_true",
+                    help="skip the FP64 run (profiling of the FP32 kernels)")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run 5 plain device-to-device copies of this many bytes (HBM "
@@ -341,8 +381,15 @@ def main():
                               oracle.Params(gamma=w.gamma))
     flops = float(ops[:4].sum())
 
+    if args.fp32_only:
+        r32 = run_precision(w, 4, args.steps, args.warmup, flops, args.tile, args.predictor)
+        print(json.dumps({"fp32_only": {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
+                                        "kernels_ms": {k: v["avg_ms"]
+                                                       for k, v in r32["kernels"].items()},
+                                        "tile": r32["tile"]}}), flush=True)
+        return
     log(f"[bench] FP64: warmup {args.warmup}, timed {args.steps} steps")
-    r64 = run_precision(w, 8, args.steps, args.warmup, flops, args.tile)
+    r64 = run_precision(w, 8, args.steps, args.warmup, flops, args.tile, args.predictor)
     log(f"[bench] FP64 {r64['value']:.4e} cell-updates/s, {r64['ms_per_step']:.2f} ms/step")
     cpu = None
     if not args.no_cpu_baseline:
@@ -355,7 +402,7 @@ def main():
     r32 = None
     if not args.no_fp32:
         log(f"[bench] FP32: warmup {args.warmup}, timed {args.steps} steps")
-        r32 = run_precision(w, 4, args.steps, args.warmup, flops, args.tile)
+        r32 = run_precision(w, 4, args.steps, args.warmup, flops, args.tile, args.predictor)
         for k in ("state_host", "dt", "bunch"):
             r32.pop(k)
         log(f"[bench] FP32 {r32['value']:.4e} cell-updates/s, {r32['ms_per_step']:.2f} ms/step")
@@ -396,7 +443,10 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": r64["update_tflops"] / peak,
-            "traffic": None,
+            "traffic": measured_traffic(r64["tile"]["chosen"], r64["tile"]["fused_predictor"]),
+            "traffic_note": "HBM bytes per update from rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled "
+                            "by a plain copy; null when the kernels or the launch configuration "
+                            "differ from the profiled ones",
             "flops_per_cell": flops,
         },
         "hbm": {

@@ -156,9 +156,17 @@ mhd_status mhd_bunch_tile_set(mhd_bunch* h, int32_t index);
 mhd_status mhd_bunch_set_predictor(mhd_bunch* h, int32_t fused);
 int32_t mhd_bunch_predictor(const mhd_bunch* h);
 
+/* Solver tile: 0 = face fluxes and edge EMFs of the tile held in shared memory together, then
+ * the whole update; 1 = two phases (face fluxes, hydro update; then edge EMFs, field update)
+ * that share the shared memory, for more work-groups per compute unit.  Same values either
+ * way.  Default 0. */
+mhd_status mhd_bunch_set_solver_split(mhd_bunch* h, int32_t split);
+int32_t mhd_bunch_solver_split(const mhd_bunch* h);
+
 /* Times every configuration on the caller's data (one warm-up and `reps` timed updates of
- * U_in -> U_out each, HIP events on `stream`) and keeps the fastest; then times both
- * predictor forms with that configuration and keeps the faster.  Synchronises `stream`;
+ * U_in -> U_out each, HIP events on `stream`) and keeps the fastest; then, with that
+ * configuration, times both solver-tile forms and then both predictor forms, keeping the
+ * faster of each.  Synchronises `stream`;
  * overwrites U_out.  best (may be NULL) receives the chosen index, ms (may be NULL, else
  * float[mhd_bunch_tile_count]) the mean update time of each configuration. */
 mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* U_in, void* U_out, const double* dt_dev,

@@ -95,6 +95,8 @@ _SIGS = {
     "mhd_bunch_graph_launch": (C.c_int, [_h, _st]),
     "mhd_bunch_set_predictor": (C.c_int, [_h, C.c_int32]),
     "mhd_bunch_predictor": (C.c_int32, [_h]),
+    "mhd_bunch_set_solver_split": (C.c_int, [_h, C.c_int32]),
+    "mhd_bunch_solver_split": (C.c_int32, [_h]),
 }
 
 KERNELS = {"prim": 0, "edge_emf_n": 1, "predict": 2, "solve": 3, "cfl": 4, "guards": 5}
@@ -262,6 +264,12 @@ class Bunch:
 
     def predictor(self):
         return int(mhd_bunch_predictor(self._h))
+
+    def set_solver_split(self, split):
+        _ok(mhd_bunch_set_solver_split(self._h, int(bool(split))), "mhd_bunch_set_solver_split")
+
+    def solver_split(self):
+        return int(mhd_bunch_solver_split(self._h))
 
     def autotune(self, U_in, U_out, dt, dx, reps=3, stream=None):
         """Time every launch configuration on these buffers and keep the fastest; returns

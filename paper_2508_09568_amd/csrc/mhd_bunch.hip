@@ -106,17 +106,28 @@ __global__ __launch_bounds__(BLK) void k_pred(const PatchDev* __restrict__ pt,
   }
 }
 
-template <typename T, int TX, int TY, int TZ>
-__global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS)) void k_solve(
+// Where the two-phase tile lets 4 work-groups of 256 share a compute unit's 160 KB of LDS,
+// the waves-per-SIMD hint asks the register allocation to match (4 waves: <= 128 VGPRs).
+template <typename T, int TX, int TY, int TZ, int SPLIT>
+struct SolveWaves {
+  static constexpr int value = (SPLIT && TileShape<TX, TY, TZ>::THREADS == 256 &&
+                                4 * TileShape<TX, TY, TZ>::LDS_SPLIT * (int)sizeof(T) <= 160 * 1024)
+                                   ? 4
+                                   : 1;
+};
+template <typename T, int TX, int TY, int TZ, int SPLIT>
+__global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS),
+                             (SolveWaves<T, TX, TY, TZ, SPLIT>::value)) void k_solve(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, const T* __restrict__ Uin,
     T* __restrict__ Uout, const T* __restrict__ S, const double* __restrict__ dt,
     const double* __restrict__ dx, Consts<T> c, int g, int ntile, int remap) {
-  __shared__ T lds[TileShape<TX, TY, TZ>::LDS_ELEMS];
+  __shared__ T lds[SPLIT ? TileShape<TX, TY, TZ>::LDS_SPLIT : TileShape<TX, TY, TZ>::LDS_ELEMS];
   DevX ex;
   for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
     const TileDev tl = tiles[logical_block(vb, ntile, remap)];
     const PatchDev& P = pt[tl.patch];
-    solve_tile<T, TX, TY, TZ>(ex, lds, P, g, tl, Uin, Uout, S, dt[tl.patch], dx + 3 * tl.patch, c);
+    solve_tile<T, TX, TY, TZ, SPLIT>(ex, lds, P, g, tl, Uin, Uout, S, dt[tl.patch],
+                                     dx + 3 * tl.patch, c);
     ex.sync();  // the next tile reuses the shared memory
   }
 }
@@ -191,8 +202,10 @@ __global__ __launch_bounds__(BLK) void k_guards(const PatchDev* __restrict__ pt,
                                                 int* status) {
   const BoxBlock b = blk[blockIdx.x];
   const PatchDev& P = pt[b.patch];
+  const int t = b.first + (int)threadIdx.x;
+  if (t >= guard_count(P)) return;
   int i, j, k;
-  if (!decode(P, BOX_ALL, g, b.first, i, j, k)) return;
+  guard_cell(P, g, t, i, j, k);
   if (guard_item(pt, b.patch, g, i, j, k, U, nbr, np)) atomicOr(status, 2);
 }
 
@@ -357,6 +370,7 @@ struct mhd_bunch {
   std::vector<TileDev> tiles[MAXSHAPE];
   // fused predictor (mhd_bunch_set_predictor): tile table over the predictor boxes
   int fused = 0;
+  int split = 0;  // two-phase solver tile (mhd_bunch_set_solver_split)
   int PXs = 8, PYs = 8, PZs = 4;
   std::vector<TileDev> ptiles;
   size_t o_ptiles = 0;
@@ -456,7 +470,7 @@ namespace {
 void add_blocks(std::vector<BoxBlock>& out, const PatchDev& P, int p, int kind, int g) {
   int lo[3], sz[3];
   box_of(P, kind, g, lo, sz);
-  const int n = sz[0] * sz[1] * sz[2];
+  const int n = kind == BOX_GUARD ? guard_count(P) : sz[0] * sz[1] * sz[2];
   for (int f = 0; f < n; f += BLK) out.push_back(BoxBlock{p, f});
 }
 
@@ -475,6 +489,22 @@ void set_shapes(mhd_bunch* h) {
 #undef MHD_ADD
 }
 
+template <typename T, int X, int Y, int Z, int SPLIT>
+void solve_launch(mhd_bunch* h, int nt, const TileDev* tl, const T* Uin, T* Uout, const T* S,
+                  const double* dt, const double* dx, const Consts<T>& c, hipStream_t s) {
+  int grid = nt;
+  if (h->mode == 2) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, reinterpret_cast<const void*>(k_solve<T, X, Y, Z, SPLIT>),
+            TileShape<X, Y, Z>::THREADS, 0) != hipSuccess || occ < 1)
+      occ = 1;
+    grid = h->persistent_grid(nt, occ);
+  }
+  hipLaunchKernelGGL((k_solve<T, X, Y, Z, SPLIT>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0,
+                     s, h->d_pt(), tl, Uin, Uout, S, dt, dx, c, h->g, nt, h->mode >= 1);
+}
+
 template <typename T>
 void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uout, const T* S,
                   const double* dt, const double* dx, const Consts<T>& c, hipStream_t s) {
@@ -484,17 +514,10 @@ void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uou
   const TileDev* tl = h->d_tiles(k) + ch.tile0[k];
 #define MHD_TRY(X, Y, Z)                                                                      \
   if (tc.x == X && tc.y == Y && tc.z == Z) {                                                  \
-    int grid = nt;                                                                            \
-    if (h->mode == 2) {                                                                       \
-      int occ = 0;                                                                            \
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                       \
-              &occ, reinterpret_cast<const void*>(k_solve<T, X, Y, Z>),                       \
-              TileShape<X, Y, Z>::THREADS, 0) != hipSuccess || occ < 1)                       \
-        occ = 1;                                                                              \
-      grid = h->persistent_grid(nt, occ);                                                     \
-    }                                                                                         \
-    hipLaunchKernelGGL((k_solve<T, X, Y, Z>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0, \
-                       s, h->d_pt(), tl, Uin, Uout, S, dt, dx, c, h->g, nt, h->mode >= 1);   \
+    if (h->split)                                                                             \
+      solve_launch<T, X, Y, Z, 1>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                    \
+    else                                                                                      \
+      solve_launch<T, X, Y, Z, 0>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                    \
     return;                                                                                   \
   }
   switch (h->act) {
@@ -587,9 +610,10 @@ mhd_status launch_cfl(mhd_bunch* h, const T* U, const double* dx, double* dt, in
 
 template <typename T>
 mhd_status launch_guards(mhd_bunch* h, T* U, const int32_t* nbr, hipStream_t s) {
-  const int nb = (int)h->blocks[BOX_ALL].size();
+  const int nb = (int)h->blocks[BOX_GUARD].size();
+  if (nb == 0) return MHD_OK;
   hipEvent_t t0 = h->tic(s);
-  hipLaunchKernelGGL(k_guards<T>, dim3(nb), dim3(BLK), 0, s, h->d_pt(), h->d_blk(BOX_ALL), U, nbr, h->g,
+  hipLaunchKernelGGL(k_guards<T>, dim3(nb), dim3(BLK), 0, s, h->d_pt(), h->d_blk(BOX_GUARD), U, nbr, h->g,
                      h->P, h->d_status());
   h->toc(s, MHD_KERNEL_GUARDS, t0);
   return h->hip_ok(hipGetLastError(), "launch guard kernel") ? MHD_OK : MHD_EDEVICE;
@@ -847,6 +871,7 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
     for (int p = ch.p0; p < ch.p1; ++p) {
       add_blocks(h->blocks[BOX_INTERIOR], h->pt[p], p, BOX_INTERIOR, g);
       add_blocks(h->blocks[BOX_ALL], h->pt[p], p, BOX_ALL, g);
+      add_blocks(h->blocks[BOX_GUARD], h->pt[p], p, BOX_GUARD, g);
     }
     ch.nblk_all = (int)h->blocks[BOX_ALL].size() - ch.blk0_all;
   }
@@ -1064,6 +1089,14 @@ mhd_status mhd_bunch_set_predictor(mhd_bunch* h, int32_t fused) {
 
 int32_t mhd_bunch_predictor(const mhd_bunch* h) { return h ? h->fused : -1; }
 
+mhd_status mhd_bunch_set_solver_split(mhd_bunch* h, int32_t split) {
+  if (!h || (split != 0 && split != 1)) return MHD_EINVAL;
+  h->split = split;
+  return MHD_OK;
+}
+
+int32_t mhd_bunch_solver_split(const mhd_bunch* h) { return h ? h->split : -1; }
+
 mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* Uin, void* Uout, const double* dt,
                               const double* dx, int32_t reps, hipStream_t s, int32_t* best,
                               float* ms) {
@@ -1095,19 +1128,22 @@ mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* Uin, void* Uout, const d
   }
   h->shape = bi / NMODE;
   h->mode = bi % NMODE;
-  // predictor: staged kernels or the fused tile kernel, with the chosen configuration
-  const int f0 = h->fused;
-  float fms[2] = {0.0f, 0.0f};
-  for (int f = 0; f < 2 && ok; ++f) {
-    h->fused = f;
-    ok = mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;
-    ok = ok && h->hip_ok(hipEventRecord(a, s), "autotune event");
-    for (int r = 0; r < reps && ok; ++r) ok = mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;
-    ok = ok && h->hip_ok(hipEventRecord(b, s), "autotune event") &&
-         h->hip_ok(hipEventSynchronize(b), "autotune sync") &&
-         h->hip_ok(hipEventElapsedTime(&fms[f], a, b), "autotune timing");
+  // then, with that configuration, the two-phase solver tile and the fused predictor
+  int* knob[2] = {&h->split, &h->fused};
+  for (int q = 0; q < 2 && ok; ++q) {
+    const int v0 = *knob[q];
+    float kms[2] = {0.0f, 0.0f};
+    for (int f = 0; f < 2 && ok; ++f) {
+      *knob[q] = f;
+      ok = mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;
+      ok = ok && h->hip_ok(hipEventRecord(a, s), "autotune event");
+      for (int r = 0; r < reps && ok; ++r) ok = mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;
+      ok = ok && h->hip_ok(hipEventRecord(b, s), "autotune event") &&
+           h->hip_ok(hipEventSynchronize(b), "autotune sync") &&
+           h->hip_ok(hipEventElapsedTime(&kms[f], a, b), "autotune timing");
+    }
+    *knob[q] = ok ? (kms[1] < kms[0] ? 1 : 0) : v0;
   }
-  h->fused = ok ? (fms[1] < fms[0] ? 1 : 0) : f0;
   if (a) (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
   h->prof = prof;

@@ -50,7 +50,8 @@ struct TileDev {    // one work-group of the solver: tile origin inside the inte
   int32_t x0, y0, z0;
 };
 
-enum BoxKind { BOX_PRIM = 0, BOX_EN = 1, BOX_PRED = 2, BOX_INTERIOR = 3, BOX_ALL = 4, NBOX = 5 };
+enum BoxKind { BOX_PRIM = 0, BOX_EN = 1, BOX_PRED = 2, BOX_INTERIOR = 3, BOX_ALL = 4, BOX_GUARD = 5,
+               NBOX = 6 };
 
 __host__ __device__ __forceinline__ bool active(const PatchDev& P, int d) { return (P.act >> d) & 1; }
 
@@ -66,6 +67,43 @@ __host__ __device__ __forceinline__ void box_of(const PatchDev& P, int kind, int
       case BOX_INTERIOR: lo[d] = g; sz[d] = P.n[d]; break;
       default: lo[d] = 0; sz[d] = P.N[d]; break;
     }
+  }
+}
+
+// Guard cells of a patch (padded box minus interior) as one index range: first the guard
+// layers normal to z (whole planes), then those normal to y inside the interior z range, then
+// those normal to x inside the interior y and z ranges.
+__host__ __device__ __forceinline__ int guard_count(const PatchDev& P) {
+  int in[3];
+  for (int d = 0; d < 3; ++d) in[d] = active(P, d) ? P.n[d] : 1;
+  return P.N[0] * P.N[1] * P.N[2] - in[0] * in[1] * in[2];
+}
+__host__ __device__ __forceinline__ void guard_cell(const PatchDev& P, int g, int t, int& i, int& j,
+                                                    int& k) {
+  const int Nx = P.N[0], Ny = P.N[1], Nz = P.N[2];
+  const int lo[3] = {active(P, 0) ? g : 0, active(P, 1) ? g : 0, active(P, 2) ? g : 0};
+  const int in[3] = {active(P, 0) ? P.n[0] : 1, active(P, 1) ? P.n[1] : 1, active(P, 2) ? P.n[2] : 1};
+  const int nz = Nz - in[2], ny = Ny - in[1], nx = Nx - in[0];  // guard layers per direction
+  const int rz = nz * Ny * Nx, ry = in[2] * ny * Nx;
+  if (t < rz) {
+    const int q = t / (Ny * Nx), r = t - q * (Ny * Nx);
+    k = q < lo[2] ? q : q + in[2];
+    j = r / Nx;
+    i = r - j * Nx;
+  } else if (t < rz + ry) {
+    t -= rz;
+    const int q = t / (ny * Nx), r = t - q * (ny * Nx);
+    k = lo[2] + q;
+    const int jj = r / Nx;
+    j = jj < lo[1] ? jj : jj + in[1];
+    i = r - jj * Nx;
+  } else {
+    t -= rz + ry;
+    const int q = t / (in[1] * nx), r = t - q * (in[1] * nx);
+    k = lo[2] + q;
+    const int jj = r / nx, ii = r - jj * nx;
+    j = lo[1] + jj;
+    i = ii < lo[0] ? ii : ii + in[0];
   }
 }
 
@@ -95,6 +133,18 @@ template <typename T>
 struct Ld {
   const T* p;
   __host__ __device__ __forceinline__ T operator()(int64_t i) const { return p[i]; }
+};
+
+// Loads from one patch's block of an array (base pointer of the block) by 32-bit element
+// index: a block is smaller than 4 GiB, so the address is the uniform base plus a 32-bit
+// byte offset and no 64-bit index arithmetic is spent per load.
+template <typename T>
+struct LdRel {
+  const T* p;
+  __host__ __device__ __forceinline__ T operator()(uint32_t i) const {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) +
+                                       (uint32_t)(i * (uint32_t)sizeof(T)));
+  }
 };
 
 template <typename T>
@@ -214,14 +264,14 @@ __host__ __device__ __forceinline__ void pred_point(const PatchDev& P, int i, in
 // ---------------------------------------------------- stage 4a: HLLD face flux
 // Face of direction d on the lower side of padded cell (i, j, k).  Returns the flux in
 // the face frame (rho, m_n, m_t1, m_t2, E) with (d, t1, t2) cyclic.  w reads the predictor
-// data (absolute index P.wbase + v Nwc + wcell).
+// data of the patch by index v Nwc + wcell relative to its block (P.wbase).
 template <typename S, class AW>
 __host__ __device__ __forceinline__ void face_point(const PatchDev& P, int g, int d, int i, int j,
                                                     int k, const AW& w, const Consts<S>& c,
                                                     S F[5]) {
-  const int64_t Nw = P.Nwc;
-  const int64_t wr = P.wbase + wcell_of(P, g, i, j, k);
-  const int64_t wl = wr - P.woff[d];
+  const uint32_t Nw = (uint32_t)P.Nwc;
+  const uint32_t wr = (uint32_t)wcell_of(P, g, i, j, k);
+  const uint32_t wl = wr - (uint32_t)P.woff[d];
   const int a = (d + 1) % 3, b = (d + 2) % 3;
   const int comp[7] = {0, 1 + d, 1 + a, 1 + b, 4, 5 + a, 5 + b};
   S s[2][7];
@@ -239,13 +289,13 @@ __host__ __device__ __forceinline__ void face_point(const PatchDev& P, int g, in
   hlld_flux(s, bn, c, F);
 }
 
-// predicted corner state of predictor cell wc (absolute) at corner (sa, sb) for an edge
-// along e: (rho, u_a, u_b, p, B_e, B_a, B_b)
+// predicted corner state of predictor cell wc (index in the patch's predictor box) at corner
+// (sa, sb) for an edge along e: (rho, u_a, u_b, p, B_e, B_a, B_b)
 template <typename S, class AW>
-__host__ __device__ __forceinline__ void corner_state(const PatchDev& P, const AW& w, int64_t wc,
+__host__ __device__ __forceinline__ void corner_state(const PatchDev& P, const AW& w, uint32_t wc,
                                                       int e, int sa, int sb, const Consts<S>& c,
                                                       S C[7]) {
-  const int64_t Nw = P.Nwc;
+  const uint32_t Nw = (uint32_t)P.Nwc;
   const int a = (e + 1) % 3, b = (e + 2) % 3;
   const int comp[5] = {0, 1 + a, 1 + b, 4, 5 + e};
   for (int t = 0; t < 5; ++t) {
@@ -254,8 +304,8 @@ __host__ __device__ __forceinline__ void corner_state(const PatchDev& P, const A
     const S hb = S(0.5) * w(wc + slope_slot(b, m) * Nw);
     C[t] = w(wc + m * Nw) + ((sa > 0 ? ha : -ha) + (sb > 0 ? hb : -hb));
   }
-  const int64_t fa = wc + (sa > 0 ? P.woff[a] : 0);
-  const int64_t fb = wc + (sb > 0 ? P.woff[b] : 0);
+  const uint32_t fa = wc + (sa > 0 ? (uint32_t)P.woff[a] : 0u);
+  const uint32_t fb = wc + (sb > 0 ? (uint32_t)P.woff[b] : 0u);
   const S ta = S(0.5) * w(fa + dbf_slot(a, b) * Nw);
   const S tb = S(0.5) * w(fb + dbf_slot(b, a) * Nw);
   C[5] = w(fa + (W_BH + a) * Nw) + (sb > 0 ? ta : -ta);
@@ -270,8 +320,8 @@ template <typename S, class AW>
 __host__ __device__ __forceinline__ S edge_point(const PatchDev& P, int g, int e, int i, int j, int k,
                                                  const AW& w, const Consts<S>& c) {
   const int a = (e + 1) % 3, b = (e + 2) % 3;
-  const int64_t wc = P.wbase + wcell_of(P, g, i, j, k);
-  const int64_t oa = P.woff[a], ob = P.woff[b];
+  const uint32_t wc = (uint32_t)wcell_of(P, g, i, j, k);
+  const uint32_t oa = (uint32_t)P.woff[a], ob = (uint32_t)P.woff[b];
   S C[4][7];
   corner_state(P, w, wc - oa - ob, e, +1, +1, c, C[0]);  // SW
   corner_state(P, w, wc - ob, e, -1, +1, c, C[1]);       // SE
@@ -281,6 +331,15 @@ __host__ __device__ __forceinline__ S edge_point(const PatchDev& P, int g, int e
 }
 
 // ------------------------------------------------ forward writers of stages 1-3
+// the NW predictor values of one cell into the patch's predictor block (32-bit offsets)
+template <typename T>
+__host__ __device__ __forceinline__ void store_w(T* base, uint32_t wcell, uint32_t Nw,
+                                                 const T w[NW]) {
+  char* b = reinterpret_cast<char*>(base);
+  for (int v = 0; v < NW; ++v)
+    *reinterpret_cast<T*>(b + (uint32_t)((wcell + (uint32_t)v * Nw) * (uint32_t)sizeof(T))) = w[v];
+}
+
 template <typename T>
 __host__ __device__ __forceinline__ int prim_item(const PatchDev& P, int64_t cell, const T* U, T* S,
                                                   const Consts<T>& c) {
@@ -305,21 +364,20 @@ __host__ __device__ __forceinline__ void pred_item(const PatchDev& P, int g, int
                                                    const double* dxp, const Consts<T>& c) {
   T w[NW];
   pred_point(P, i, j, k, Ld<T>{U}, Ld<T>{S}, Ld<T>{S}, dt, dxp, c, w);
-  T* o = Wout + P.wbase + wcell_of(P, g, i, j, k);
-  for (int v = 0; v < NW; ++v) o[v * P.Nwc] = w[v];
+  store_w(Wout + P.wbase, (uint32_t)wcell_of(P, g, i, j, k), (uint32_t)P.Nwc, w);
 }
 
 template <typename T>
 __host__ __device__ __forceinline__ void face_flux_item(const PatchDev& P, int g, int d, int i, int j,
                                                         int k, const T* Win, const Consts<T>& c,
                                                         T F[5]) {
-  face_point(P, g, d, i, j, k, Ld<T>{Win}, c, F);
+  face_point(P, g, d, i, j, k, LdRel<T>{Win + P.wbase}, c, F);
 }
 
 template <typename T>
 __host__ __device__ __forceinline__ T edge_emf_item(const PatchDev& P, int g, int e, int i, int j, int k,
                                                     const T* Win, const Consts<T>& c) {
-  return edge_point(P, g, e, i, j, k, Ld<T>{Win}, c);
+  return edge_point(P, g, e, i, j, k, LdRel<T>{Win + P.wbase}, c);
 }
 
 // -------------------------------------------------------------- time step
@@ -489,7 +547,7 @@ __host__ __device__ __forceinline__ T adj_w_item(const PatchDev& P, int g, const
                                                  const double* dxp, const Consts<T>& c) {
   typedef Dual<T> S;
   const Consts<S> cd = lift<S>(c);
-  const LdSeed<T> acc{W, P.wbase + (int64_t)v * P.Nwc + wcell_of(P, g, x[0], x[1], x[2])};
+  const LdSeed<T> acc{W + P.wbase, (int64_t)v * P.Nwc + wcell_of(P, g, x[0], x[1], x[2])};
   const T dtdx[3] = {T(dt / dxp[0]), T(dt / dxp[1]), T(dt / dxp[2])};
   T sum = T(0);
   for (int d = 0; d < 3; ++d) {
@@ -700,8 +758,7 @@ __host__ __device__ __forceinline__ int predict_tile(X& ex, T* L, const PatchDev
     const int gi = active(P, 0) ? o3[0] + ti : 0;
     const int gj = active(P, 1) ? o3[1] + tj : 0;
     const int gk = active(P, 2) ? o3[2] + tk : 0;
-    T* o = W + P.wbase + wcell_of(P, g, gi, gj, gk);
-    for (int v = 0; v < NW; ++v) o[v * P.Nwc] = w[v];
+    store_w(W + P.wbase, (uint32_t)wcell_of(P, g, gi, gj, gk), (uint32_t)P.Nwc, w);
   }
   return bad;
 }
@@ -725,11 +782,15 @@ struct TileShape {
   static constexpr int NEZ = (TX + 1) * (TY + 1) * TZ, NEX = TX * (TY + 1) * (TZ + 1),
                        NEY = (TX + 1) * TY * (TZ + 1);
   static constexpr int LDS_ELEMS = 5 * (NFX + NFY + NFZ) + NEZ + NEX + NEY;
+  // two-phase tile (faces and hydro update, then edges and field update): the flux and EMF
+  // arrays take turns in the same shared memory
+  static constexpr int NFLUX = 5 * (NFX + NFY + NFZ), NEMF = NEZ + NEX + NEY;
+  static constexpr int LDS_SPLIT = NFLUX > NEMF ? NFLUX : NEMF;
   static constexpr int THREADS = TX * TY * TZ < 64 ? 64 : TX * TY * TZ;
   static_assert(THREADS % 64 == 0, "solver work-groups are whole wavefronts");
 };
 
-template <typename T, int TX, int TY, int TZ, class X>
+template <typename T, int TX, int TY, int TZ, int SPLIT, class X>
 __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDev& P, int g,
                                                     const TileDev& tl, const T* Uin, T* Uout,
                                                     const T* Win, double dt, const double* dxp,
@@ -738,7 +799,7 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
   T* fx = lds;
   T* fy = fx + 5 * SH::NFX;
   T* fz = fy + 5 * SH::NFY;
-  T* ez = fz + 5 * SH::NFZ;
+  T* ez = SPLIT ? lds : fz + 5 * SH::NFZ;
   T* exx = ez + SH::NEZ;
   T* ey = exx + SH::NEX;
   const int ax = active(P, 0), ay = active(P, 1), az = active(P, 2);
@@ -753,81 +814,105 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
   // each padded to whole wavefronts.  The work-group size is a multiple of the wavefront,
   // so every wavefront works on one segment per round: the face/edge branch and the
   // direction-dependent offsets stay uniform across its lanes, and the rounds are shared
-  // by all segments instead of each direction leaving a ragged last round.
+  // by all segments instead of each direction leaving a ragged last round.  Segment k has
+  // the compile-time extent of a full tile (so the item index splits by constants); items
+  // beyond the tile's actual extent (ragged tiles, collapsed directions) are skipped.
+  // SPLIT: faces first (then the hydro update), edges after (then the field update), so
+  // flux and EMF arrays share the shared memory.
   constexpr int WAVE = 64;
-  int cnt[6], beg[7];
-  beg[0] = 0;
-  for (int d = 0; d < 3; ++d) {
-    cnt[d] = active(P, d) ? (tx + (d == 0)) * (ty + (d == 1)) * (tz + (d == 2)) : 0;
-    cnt[3 + d] = (tx + (d != 0 && ax)) * (ty + (d != 1 && ay)) * (tz + (d != 2 && az));
-  }
-  for (int k = 0; k < 6; ++k) beg[k + 1] = beg[k] + (cnt[k] + WAVE - 1) / WAVE * WAVE;
-  for (int it = tid; it < beg[6]; it += nth) {
-    int k = 0;
-    while (k < 5 && it >= beg[k + 1]) ++k;
-    k = wave_uniform(k);
-    const int r = it - beg[k];
-    if (r >= cnt[k]) continue;
-    if (k < 3) {
-      // face normal to d: local extents t + 1 along d
-      const int d = k;
-      const int e0 = tx + (d == 0), e1 = ty + (d == 1);
-      const int lx = r % e0, ly = (r / e0) % e1, lz = r / (e0 * e1);
-      const int LX = TX + (d == 0), LY = TY + (d == 1);
-      T* fd = d == 0 ? fx : (d == 1 ? fy : fz);
-      const int NF = d == 0 ? SH::NFX : (d == 1 ? SH::NFY : SH::NFZ);
-      const int a = (d + 1) % 3, b = (d + 2) % 3;
-      T F[5];
-      face_flux_item(P, g, d, i0 + lx, j0 + ly, k0 + lz, Win, c, F);
-      const int li = lx + LX * (ly + LY * lz);
-      fd[0 * NF + li] = F[0];
-      fd[(1 + d) * NF + li] = F[1];
-      fd[(1 + a) * NF + li] = F[2];
-      fd[(1 + b) * NF + li] = F[3];
-      fd[4 * NF + li] = F[4];
-    } else {
-      // edge along e: extents t + 1 along the two transverse directions when active
-      const int e = k - 3;
-      const int e0 = tx + (e != 0 && ax), e1 = ty + (e != 1 && ay);
-      const int lx = r % e0, ly = (r / e0) % e1, lz = r / (e0 * e1);
-      const int LX = TX + (e != 0), LY = TY + (e != 1);
-      T* ed = e == 0 ? exx : (e == 1 ? ey : ez);
-      ed[lx + LX * (ly + LY * lz)] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
-    }
-  }
-  ex.sync();
-
+  constexpr int X1 = TX > 1 ? TX + 1 : 1, Y1 = TY > 1 ? TY + 1 : 1, Z1 = TZ > 1 ? TZ + 1 : 1;
+  constexpr int NS[6] = {X1 * TY * TZ, TX * Y1 * TZ, TX * TY * Z1,
+                         TX * Y1 * Z1, X1 * TY * Z1, X1 * Y1 * TZ};
+  constexpr int B1 = (NS[0] + WAVE - 1) / WAVE * WAVE, B2 = B1 + (NS[1] + WAVE - 1) / WAVE * WAVE,
+                B3 = B2 + (NS[2] + WAVE - 1) / WAVE * WAVE, B4 = B3 + (NS[3] + WAVE - 1) / WAVE * WAVE,
+                B5 = B4 + (NS[4] + WAVE - 1) / WAVE * WAVE, B6 = B5 + (NS[5] + WAVE - 1) / WAVE * WAVE;
+  const int fact[3] = {ax, ay, az};
   const T dtdx[3] = {T(dt / dxp[0]), T(dt / dxp[1]), T(dt / dxp[2])};
   const int ncell = tx * ty * tz;
   const int64_t Nc = P.Nc;
-  for (int it = tid; it < ncell; it += nth) {
-    const int lx = it % tx, ly = (it / tx) % ty, lz = it / (tx * ty);
-    const int64_t cell = cell_of(P, i0 + lx, j0 + ly, k0 + lz);
-    const T* u = Uin + P.ubase;
-    T* uo = Uout + P.ubase;
-    const int fxl = lx + (TX + 1) * (ly + TY * lz), fyl = lx + TX * (ly + (TY + 1) * lz),
-              fzl = lx + TX * (ly + TY * lz);
-    for (int m = 0; m < 5; ++m) {
-      T v = u[m * Nc + cell];
-      if (ax) v = v - dtdx[0] * (fx[m * SH::NFX + fxl + 1] - fx[m * SH::NFX + fxl]);
-      if (ay) v = v - dtdx[1] * (fy[m * SH::NFY + fyl + TX] - fy[m * SH::NFY + fyl]);
-      if (az) v = v - dtdx[2] * (fz[m * SH::NFZ + fzl + TX * TY] - fz[m * SH::NFZ + fzl]);
-      uo[m * Nc + cell] = v;
+  const T* u = Uin + P.ubase;
+  T* uo = Uout + P.ubase;
+
+  for (int phase = 0; phase < (SPLIT ? 2 : 1); ++phase) {
+    const int ibeg = SPLIT && phase == 1 ? B3 : 0;
+    const int iend = SPLIT && phase == 0 ? B3 : B6;
+    for (int it = ibeg + tid; it < iend; it += nth) {
+      const int k = wave_uniform(it < B1 ? 0 : it < B2 ? 1 : it < B3 ? 2 : it < B4 ? 3 : it < B5 ? 4 : 5);
+      int lx, ly, lz, e0, e1, e2;
+      switch (k) {
+        case 0: { const int r = it;      lx = r % X1; ly = (r / X1) % TY; lz = r / (X1 * TY); break; }
+        case 1: { const int r = it - B1; lx = r % TX; ly = (r / TX) % Y1; lz = r / (TX * Y1); break; }
+        case 2: { const int r = it - B2; lx = r % TX; ly = (r / TX) % TY; lz = r / (TX * TY); break; }
+        case 3: { const int r = it - B3; lx = r % TX; ly = (r / TX) % Y1; lz = r / (TX * Y1); break; }
+        case 4: { const int r = it - B4; lx = r % X1; ly = (r / X1) % TY; lz = r / (X1 * TY); break; }
+        default: { const int r = it - B5; lx = r % X1; ly = (r / X1) % Y1; lz = r / (X1 * Y1); break; }
+      }
+      if (k < 3) {
+        // face normal to d: actual extents t + 1 along d; none for a collapsed d
+        const int d = k;
+        if (!fact[d]) continue;
+        e0 = tx + (d == 0);
+        e1 = ty + (d == 1);
+        e2 = tz + (d == 2);
+        if (lx >= e0 || ly >= e1 || lz >= e2) continue;
+        const int LX = TX + (d == 0), LY = TY + (d == 1);
+        T* fd = d == 0 ? fx : (d == 1 ? fy : fz);
+        const int NF = d == 0 ? SH::NFX : (d == 1 ? SH::NFY : SH::NFZ);
+        const int a = (d + 1) % 3, b = (d + 2) % 3;
+        T F[5];
+        face_flux_item(P, g, d, i0 + lx, j0 + ly, k0 + lz, Win, c, F);
+        const int li = lx + LX * (ly + LY * lz);
+        fd[0 * NF + li] = F[0];
+        fd[(1 + d) * NF + li] = F[1];
+        fd[(1 + a) * NF + li] = F[2];
+        fd[(1 + b) * NF + li] = F[3];
+        fd[4 * NF + li] = F[4];
+      } else {
+        // edge along e: extents t + 1 along the two transverse directions when active
+        const int e = k - 3;
+        e0 = tx + (e != 0 && ax);
+        e1 = ty + (e != 1 && ay);
+        e2 = tz + (e != 2 && az);
+        if (lx >= e0 || ly >= e1 || lz >= e2) continue;
+        const int LX = TX + (e != 0), LY = TY + (e != 1);
+        T* ed = e == 0 ? exx : (e == 1 ? ey : ez);
+        ed[lx + LX * (ly + LY * lz)] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
+      }
     }
-    // edge arrays: ez (TX+1)x(TY+1)xTZ, ex TXx(TY+1)x(TZ+1), ey (TX+1)xTYx(TZ+1)
-    const int zl = lx + (TX + 1) * (ly + (TY + 1) * lz);
-    const int xl = lx + TX * (ly + (TY + 1) * lz);
-    const int yl = lx + (TX + 1) * (ly + TY * lz);
-    T bx = u[5 * Nc + cell], by = u[6 * Nc + cell], bz = u[7 * Nc + cell];
-    if (ay) bx = bx + dtdx[1] * (ez[zl + (TX + 1)] - ez[zl]);
-    if (az) bx = bx - dtdx[2] * (ey[yl + (TX + 1) * TY] - ey[yl]);
-    if (az) by = by + dtdx[2] * (exx[xl + TX * (TY + 1)] - exx[xl]);
-    if (ax) by = by - dtdx[0] * (ez[zl + 1] - ez[zl]);
-    if (ax) bz = bz + dtdx[0] * (ey[yl + 1] - ey[yl]);
-    if (ay) bz = bz - dtdx[1] * (exx[xl + TX] - exx[xl]);
-    uo[5 * Nc + cell] = bx;
-    uo[6 * Nc + cell] = by;
-    uo[7 * Nc + cell] = bz;
+    ex.sync();
+
+    for (int it = tid; it < ncell; it += nth) {
+      const int lx = it % tx, ly = (it / tx) % ty, lz = it / (tx * ty);
+      const int64_t cell = cell_of(P, i0 + lx, j0 + ly, k0 + lz);
+      if (!SPLIT || phase == 0) {
+        const int fxl = lx + (TX + 1) * (ly + TY * lz), fyl = lx + TX * (ly + (TY + 1) * lz),
+                  fzl = lx + TX * (ly + TY * lz);
+        for (int m = 0; m < 5; ++m) {
+          T v = u[m * Nc + cell];
+          if (ax) v = v - dtdx[0] * (fx[m * SH::NFX + fxl + 1] - fx[m * SH::NFX + fxl]);
+          if (ay) v = v - dtdx[1] * (fy[m * SH::NFY + fyl + TX] - fy[m * SH::NFY + fyl]);
+          if (az) v = v - dtdx[2] * (fz[m * SH::NFZ + fzl + TX * TY] - fz[m * SH::NFZ + fzl]);
+          uo[m * Nc + cell] = v;
+        }
+      }
+      if (!SPLIT || phase == 1) {
+        // edge arrays: ez (TX+1)x(TY+1)xTZ, ex TXx(TY+1)x(TZ+1), ey (TX+1)xTYx(TZ+1)
+        const int zl = lx + (TX + 1) * (ly + (TY + 1) * lz);
+        const int xl = lx + TX * (ly + (TY + 1) * lz);
+        const int yl = lx + (TX + 1) * (ly + TY * lz);
+        T bx = u[5 * Nc + cell], by = u[6 * Nc + cell], bz = u[7 * Nc + cell];
+        if (ay) bx = bx + dtdx[1] * (ez[zl + (TX + 1)] - ez[zl]);
+        if (az) bx = bx - dtdx[2] * (ey[yl + (TX + 1) * TY] - ey[yl]);
+        if (az) by = by + dtdx[2] * (exx[xl + TX * (TY + 1)] - exx[xl]);
+        if (ax) by = by - dtdx[0] * (ez[zl + 1] - ez[zl]);
+        if (ax) bz = bz + dtdx[0] * (ey[yl + 1] - ey[yl]);
+        if (ay) bz = bz - dtdx[1] * (exx[xl + TX] - exx[xl]);
+        uo[5 * Nc + cell] = bx;
+        uo[6 * Nc + cell] = by;
+        uo[7 * Nc + cell] = bz;
+      }
+    }
+    if (SPLIT && phase == 0) ex.sync();  // the edge phase overwrites the fluxes
   }
 }
 

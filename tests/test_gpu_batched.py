@@ -1,5 +1,5 @@
 """Batched dispatch on the GPU: every launch configuration (solver tile shape x launch mode,
-staged or fused predictor) gives the same bits, the autotuner keeps a valid one, and a multi-step run captured in one
+one- or two-phase solver tile, staged or fused predictor) gives the same bits, the autotuner keeps a valid one, and a multi-step run captured in one
 HIP graph (per-patch local dt, or guard exchange + global dt) reproduces the eager calls
 bitwise on every replay and the oracle's run step for step."""
 import numpy as np
@@ -41,14 +41,17 @@ def test_every_launch_configuration_gives_identical_bits(case):
     for fused in (0, 1):
         B.set_predictor(fused)
         assert B.predictor() == fused
-        for i, cfg in enumerate(cfgs):
-            B.set_tile(i)
-            Uo = dev(np.zeros_like(U))
-            B.update(Ui, Uo, dtd, dxd)
-            assert B.check() == 0
-            outs.append(host(Uo))
-            log(f"    predictor {fused} config {i} {cfg}: max|diff| vs first = "
-                f"{np.abs(outs[-1] - outs[0]).max():.3e}")
+        for split in (0, 1):
+            B.set_solver_split(split)
+            assert B.solver_split() == split
+            for i, cfg in enumerate(cfgs):
+                B.set_tile(i)
+                Uo = dev(np.zeros_like(U))
+                B.update(Ui, Uo, dtd, dxd)
+                assert B.check() == 0
+                outs.append(host(Uo))
+                log(f"    predictor {fused} split {split} config {i} {cfg}: max|diff| vs first = "
+                    f"{np.abs(outs[-1] - outs[0]).max():.3e}")
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     err = rel_err_fields(L, outs[0], ref)
