@@ -67,7 +67,8 @@ def algorithmic_bytes_per_cell(n, g, s):
     return 8.0 * s * (((n + 2 * g) / n) ** 3 + 1.0)
 
 
-def run_precision(w, precision, steps, warmup, flops_per_cell, tile=None, predictor=None):
+def run_precision(w, precision, steps, warmup, flops_per_cell, tile=None, predictor=None,
+                  split=None):
     import numpy as np
     import torch
 
@@ -100,6 +101,8 @@ def run_precision(w, precision, steps, warmup, flops_per_cell, tile=None, predic
         B.set_tile(tile)
     if predictor is not None:
         B.set_predictor(predictor)
+    if split is not None:
+        B.set_solver_split(split)
     for _ in range(warmup):
         step(Ua, Ub)
         Ua, Ub = Ub, Ua
@@ -341,6 +344,8 @@ def main():
                     help="use this launch configuration instead of autotuning")
     ap.add_argument("--predictor", type=int, default=None, choices=(0, 1),
                     help="force the staged (0) or fused (1) predictor")
+    ap.add_argument("--split", type=int, default=None, choices=(0, 1),
+                    help="force the one- (0) or two-phase (1) solver tile")
     ap.add_argument("--fp32-only", action="store_true",
                     help="skip the FP64 run (profiling of the FP32 kernels)")
     ap.add_argument("--batched-steps", type=int, default=10)
@@ -382,14 +387,16 @@ def main():
     flops = float(ops[:4].sum())
 
     if args.fp32_only:
-        r32 = run_precision(w, 4, args.steps, args.warmup, flops, args.tile, args.predictor)
+        r32 = run_precision(w, 4, args.steps, args.warmup, flops, args.tile, args.predictor,
+                            args.split)
         print(json.dumps({"fp32_only": {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
                                         "kernels_ms": {k: v["avg_ms"]
                                                        for k, v in r32["kernels"].items()},
                                         "tile": r32["tile"]}}), flush=True)
         return
     log(f"[bench] FP64: warmup {args.warmup}, timed {args.steps} steps")
-    r64 = run_precision(w, 8, args.steps, args.warmup, flops, args.tile, args.predictor)
+    r64 = run_precision(w, 8, args.steps, args.warmup, flops, args.tile, args.predictor,
+                        args.split)
     log(f"[bench] FP64 {r64['value']:.4e} cell-updates/s, {r64['ms_per_step']:.2f} ms/step")
     cpu = None
     if not args.no_cpu_baseline:
@@ -402,7 +409,8 @@ def main():
     r32 = None
     if not args.no_fp32:
         log(f"[bench] FP32: warmup {args.warmup}, timed {args.steps} steps")
-        r32 = run_precision(w, 4, args.steps, args.warmup, flops, args.tile, args.predictor)
+        r32 = run_precision(w, 4, args.steps, args.warmup, flops, args.tile, args.predictor,
+                            args.split)
         for k in ("state_host", "dt", "bunch"):
             r32.pop(k)
         log(f"[bench] FP32 {r32['value']:.4e} cell-updates/s, {r32['ms_per_step']:.2f} ms/step")

@@ -132,8 +132,11 @@ __global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS),
   }
 }
 
+// 256-thread tiles: three work-groups per compute unit fit the shared memory of FP64 tiles;
+// the hint keeps the registers within three waves per SIMD to match
 template <typename T, int PX, int PY, int PZ>
-__global__ __launch_bounds__((PredShape<PX, PY, PZ>::THREADS)) void k_predict(
+__global__ __launch_bounds__((PredShape<PX, PY, PZ>::THREADS),
+                             (PredShape<PX, PY, PZ>::THREADS == 256 ? 3 : 1)) void k_predict(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, const T* __restrict__ U,
     T* __restrict__ W, const double* __restrict__ dt, const double* __restrict__ dx, Consts<T> c,
     int g, int* status, int ntile, int remap) {

@@ -186,19 +186,43 @@ __host__ __device__ __forceinline__ int prim_point(const PatchDev& P, int64_t ce
 // plane): 4-cell average velocities, 2-face average fields.  q reads primitives (absolute
 // index P.sbase + m Nc + cell), u reads U.
 template <typename S, class AQ, class AU>
+__host__ __device__ __forceinline__ S en_comp(const PatchDev& P, int64_t cell, int e, const AQ& q,
+                                              const AU& u) {
+  const int64_t Nc = P.Nc, qb = P.sbase + cell, ub = P.ubase + cell;
+  const int a = (e + 1) % 3, b = (e + 2) % 3;
+  const int64_t oa = P.off[a], ob = P.off[b];
+  const int64_t qa = qb + (1 + a) * Nc, qbb = qb + (1 + b) * Nc;
+  const S va = S(0.25) * (q(qa) + q(qa - oa) + q(qa - ob) + q(qa - oa - ob));
+  const S vb = S(0.25) * (q(qbb) + q(qbb - oa) + q(qbb - ob) + q(qbb - oa - ob));
+  const S ba = S(0.5) * (u(ub + (5 + a) * Nc) + u(ub + (5 + a) * Nc - ob));
+  const S bb = S(0.5) * (u(ub + (5 + b) * Nc) + u(ub + (5 + b) * Nc - oa));
+  return va * bb - vb * ba;
+}
+template <typename S, class AQ, class AU>
 __host__ __device__ __forceinline__ void en_point(const PatchDev& P, int64_t cell, const AQ& q,
                                                   const AU& u, S E[3]) {
-  const int64_t Nc = P.Nc, qb = P.sbase + cell, ub = P.ubase + cell;
-  for (int e = 0; e < 3; ++e) {
-    const int a = (e + 1) % 3, b = (e + 2) % 3;
-    const int64_t oa = P.off[a], ob = P.off[b];
-    const int64_t qa = qb + (1 + a) * Nc, qbb = qb + (1 + b) * Nc;
-    const S va = S(0.25) * (q(qa) + q(qa - oa) + q(qa - ob) + q(qa - oa - ob));
-    const S vb = S(0.25) * (q(qbb) + q(qbb - oa) + q(qbb - ob) + q(qbb - oa - ob));
-    const S ba = S(0.5) * (u(ub + (5 + a) * Nc) + u(ub + (5 + a) * Nc - ob));
-    const S bb = S(0.5) * (u(ub + (5 + b) * Nc) + u(ub + (5 + b) * Nc - oa));
-    E[e] = va * bb - vb * ba;
-  }
+  for (int e = 0; e < 3; ++e) E[e] = en_comp<S>(P, cell, e, q, u);
+}
+
+// Edge EMFs at time n evaluated where they are read: the predictor reads E_e of cell c + o
+// through e_at(e, comp, eb, Nc, o) with eb = P.sbase + 8 Nc + c; an ordinary accessor loads
+// element eb + comp Nc + o, EnOnTheFly computes the value from the primitives and face fields
+// instead (the fused predictor keeps only those in shared memory).
+template <typename S, class AQ, class AU>
+struct EnOnTheFly {
+  const PatchDev& P;
+  const AQ& q;
+  const AU& u;
+};
+template <class AE>
+__host__ __device__ __forceinline__ auto e_at(const AE& e, int comp, int64_t eb, int64_t Nc,
+                                              int64_t o) -> decltype(e(eb)) {
+  return e(eb + comp * Nc + o);
+}
+template <typename S, class AQ, class AU>
+__host__ __device__ __forceinline__ S e_at(const EnOnTheFly<S, AQ, AU>& e, int comp, int64_t eb,
+                                           int64_t Nc, int64_t o) {
+  return en_comp<S>(e.P, eb - e.P.sbase - 8 * Nc + o, comp, e.q, e.u);
 }
 
 // ------------------------------------------------------ stage 3: predictor data
@@ -214,16 +238,20 @@ __host__ __device__ __forceinline__ void pred_point(const PatchDev& P, int i, in
   const int64_t cell = cell_of(P, i, j, k);
   const int64_t qb = P.sbase + cell, ub = P.ubase + cell, eb = P.sbase + 8 * Nc + cell;
   S qc[8];
+  #pragma unroll
   for (int m = 0; m < 8; ++m) qc[m] = q(qb + m * Nc);
   S D[3][8];
   S ix[3];
+  #pragma unroll
   for (int d = 0; d < 3; ++d) {
     ix[d] = S(1.0 / dxp[d]);
     if (!active(P, d)) {
+      #pragma unroll
       for (int m = 0; m < 8; ++m) D[d][m] = S(0);
       continue;
     }
     const int64_t o = P.off[d];
+    #pragma unroll
     for (int m = 0; m < 8; ++m) {
       if (m == 5 + d)
         D[d][m] = u(ub + (5 + d) * Nc + o) - u(ub + (5 + d) * Nc);
@@ -234,21 +262,29 @@ __host__ __device__ __forceinline__ void pred_point(const PatchDev& P, int i, in
   S r[8];
   prim_rate(qc, D, ix, c.gamma, r);
   const S hdt = S(0.5 * dt);
+  #pragma unroll
   for (int m = 0; m < 8; ++m) w[W_QT + m] = qc[m] + hdt * r[m];
+  #pragma unroll
   for (int d = 0; d < 3; ++d)
+    #pragma unroll
     for (int m = 0; m < 8; ++m)
       if (m != 5 + d) w[slope_slot(d, m)] = D[d][m];
   // half-step face field B^{n+1/2} = B^n + dt/2 curl E^n on the three lower faces
+  #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int a = (d + 1) % 3, b = (d + 2) % 3;
     S v = u(ub + (5 + d) * Nc);
-    if (active(P, a)) v = v + S(0.5 * dt / dxp[a]) * (e(eb + b * Nc + P.off[a]) - e(eb + b * Nc));
-    if (active(P, b)) v = v - S(0.5 * dt / dxp[b]) * (e(eb + a * Nc + P.off[b]) - e(eb + a * Nc));
+    if (active(P, a))
+      v = v + S(0.5 * dt / dxp[a]) * (e_at(e, b, eb, Nc, P.off[a]) - e_at(e, b, eb, Nc, 0));
+    if (active(P, b))
+      v = v - S(0.5 * dt / dxp[b]) * (e_at(e, a, eb, Nc, P.off[b]) - e_at(e, a, eb, Nc, 0));
     w[W_BH + d] = v;
   }
   // transverse slopes of the face fields (used by the corner states of the edges)
+  #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int64_t B = ub + (5 + d) * Nc;
+    #pragma unroll
     for (int f = 0; f < 3; ++f) {
       if (f == d) continue;
       S sl = S(0);
@@ -676,16 +712,16 @@ __host__ __device__ __forceinline__ T adj_u_item(const PatchDev& P, int g, const
 
 // ------------------------------------------------ fused predictor tile (stages 1-3)
 // One tile of the predictor box [g-1, g+n+1): primitives and face fields of the tile plus one
-// cell around it go to shared memory L, then the edge EMFs at time n of the tile's cells and
-// the layer above, then the 38 predictor values of the tile's cells -> W.  Stages 1-3 read
-// shared memory through a patch description F of the local box (Q fields at [0, 8 Nl), E at
-// [8 Nl, 11 Nl), face fields at [11 Nl, 14 Nl) with F.ubase = 6 Nl), so the point functions
-// are the ones of the staged kernels.  Returns 1 if a non-physical state was met.
+// cell around it go to shared memory L, then the 38 predictor values of the tile's cells ->
+// W, with the edge EMFs at time n evaluated from L where the predictor reads them.  Stages
+// 1-3 read shared memory through a patch description F of the local box (Q fields at
+// [0, 8 Nl), face fields at [8 Nl, 11 Nl) with F.ubase = 3 Nl), so the point functions are
+// the ones of the staged kernels.  Returns 1 if a non-physical state was met.
 template <int PX, int PY, int PZ>
 struct PredShape {
   static constexpr int LX = PX > 1 ? PX + 2 : 1, LY = PY > 1 ? PY + 2 : 1, LZ = PZ > 1 ? PZ + 2 : 1;
   static constexpr int NL = LX * LY * LZ;
-  static constexpr int LDS_ELEMS = 14 * NL;
+  static constexpr int LDS_ELEMS = 11 * NL;
   static constexpr int THREADS = PX * PY * PZ < 64 ? 64 : PX * PY * PZ;
 };
 
@@ -715,7 +751,7 @@ __host__ __device__ __forceinline__ int predict_tile(X& ex, T* L, const PatchDev
   F.off[1] = active(P, 1) ? l3[0] : 0;
   F.off[2] = active(P, 2) ? (int64_t)l3[0] * l3[1] : 0;
   F.sbase = 0;
-  F.ubase = 6 * F.Nc;
+  F.ubase = 3 * F.Nc;
   const int64_t Nl = F.Nc;
   const int tid = ex.tid(), nth = ex.nthr();
   int bad = 0;
@@ -729,32 +765,19 @@ __host__ __device__ __forceinline__ int predict_tile(X& ex, T* L, const PatchDev
     T q[8];
     bad |= prim_point(P, gc, Ld<T>{U}, c, q);
     for (int m = 0; m < 8; ++m) L[m * Nl + it] = q[m];
-    for (int d = 0; d < 3; ++d) L[(11 + d) * Nl + it] = U[P.ubase + (5 + d) * P.Nc + gc];
+    for (int d = 0; d < 3; ++d) L[(8 + d) * Nl + it] = U[P.ubase + (5 + d) * P.Nc + gc];
   }
   ex.sync();
-  // 2. edge EMFs at time n on local cells [1, l) of the active directions
-  int m3[3], lo3[3];
-  for (int d = 0; d < 3; ++d) {
-    m3[d] = active(P, d) ? l3[d] - 1 : 1;
-    lo3[d] = active(P, d) ? 1 : 0;
-  }
-  const int ne = m3[0] * m3[1] * m3[2];
-  for (int it = tid; it < ne; it += nth) {
-    const int li = lo3[0] + it % m3[0], lj = lo3[1] + (it / m3[0]) % m3[1],
-              lk = lo3[2] + it / (m3[0] * m3[1]);
-    const int64_t lc = cell_of(F, li, lj, lk);
-    T E[3];
-    en_point(F, lc, Ld<T>{L}, Ld<T>{L}, E);
-    for (int e = 0; e < 3; ++e) L[(8 + e) * Nl + lc] = E[e];
-  }
-  ex.sync();
-  // 3. predictor values of the tile's cells
+  // 2. predictor values of the tile's cells (local [1, e + 1) in active directions)
+  int lo3[3];
+  for (int d = 0; d < 3; ++d) lo3[d] = active(P, d) ? 1 : 0;
+  const Ld<T> lq{L};
+  const EnOnTheFly<T, Ld<T>, Ld<T>> le{F, lq, lq};
   const int nt = e3[0] * e3[1] * e3[2];
   for (int it = tid; it < nt; it += nth) {
     const int ti = it % e3[0], tj = (it / e3[0]) % e3[1], tk = it / (e3[0] * e3[1]);
     T w[NW];
-    pred_point(F, lo3[0] + ti, lo3[1] + tj, lo3[2] + tk, Ld<T>{L}, Ld<T>{L}, Ld<T>{L}, dt, dxp, c,
-               w);
+    pred_point(F, lo3[0] + ti, lo3[1] + tj, lo3[2] + tk, lq, lq, le, dt, dxp, c, w);
     const int gi = active(P, 0) ? o3[0] + ti : 0;
     const int gj = active(P, 1) ? o3[1] + tj : 0;
     const int gk = active(P, 2) ? o3[2] + tk : 0;
