@@ -38,9 +38,12 @@ def log(*a):
 # 1 GiB device copy (FETCH_SIZE reads 0.5x there, WRITE_SIZE 1x); see profiles/.  Valid only
 # for the kernel sources it was measured on: reported as null once they change.
 MEASURED_TRAFFIC = {
-    "sources_sha256": None,
-    "bytes_per_update": None,
-    "profile": None,
+    "sources_sha256": "2ed2778b7bba8a42e63e1be0e5f98932b9d73125ecb252ba220bfbdaa3b41c10",
+    "tile": [32, 4, 2, 1],
+    "fused_predictor": 1,
+    "solver_split": 0,
+    "bytes_per_update": 1.8422e11,
+    "profile": "profiles/mhd_update_turbulence512_pmc.md",
 }
 
 
@@ -54,10 +57,10 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(tile, fused):
+def measured_traffic(tile, fused, split):
     m = MEASURED_TRAFFIC
     if m["sources_sha256"] != kernel_sources_sha256() or m.get("tile") != list(tile) or \
-            m.get("fused_predictor") != fused:
+            m.get("fused_predictor") != fused or m.get("solver_split") != split:
         return None
     return m["bytes_per_update"]
 
@@ -451,7 +454,8 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": r64["update_tflops"] / peak,
-            "traffic": measured_traffic(r64["tile"]["chosen"], r64["tile"]["fused_predictor"]),
+            "traffic": measured_traffic(r64["tile"]["chosen"], r64["tile"]["fused_predictor"],
+                                        r64["tile"]["solver_split"]),
             "traffic_note": "HBM bytes per update from rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled "
                             "by a plain copy; null when the kernels or the launch configuration "
                             "differ from the profiled ones",
