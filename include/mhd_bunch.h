@@ -163,12 +163,12 @@ int32_t mhd_bunch_predictor(const mhd_bunch* h);
 mhd_status mhd_bunch_set_solver_split(mhd_bunch* h, int32_t split);
 int32_t mhd_bunch_solver_split(const mhd_bunch* h);
 
-/* Times every configuration on the caller's data (one warm-up and `reps` timed updates of
- * U_in -> U_out each, HIP events on `stream`) and keeps the fastest; then, with that
- * configuration, times both solver-tile forms and then both predictor forms, keeping the
- * faster of each.  Synchronises `stream`;
- * overwrites U_out.  best (may be NULL) receives the chosen index, ms (may be NULL, else
- * float[mhd_bunch_tile_count]) the mean update time of each configuration. */
+/* Times every configuration, each with both solver-tile forms, on the caller's data (one
+ * warm-up and `reps` timed updates of U_in -> U_out each, HIP events on `stream`) and keeps
+ * the fastest pair; then, with it, times both predictor forms and keeps the faster.
+ * Synchronises `stream`; overwrites U_out.  best (may be NULL) receives the chosen
+ * configuration index, ms (may be NULL, else float[mhd_bunch_tile_count]) the mean update
+ * time of each configuration (the faster of its two solver forms). */
 mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* U_in, void* U_out, const double* dt_dev,
                               const double* dx_dev, int32_t reps, hipStream_t stream,
                               int32_t* best, float* ms);

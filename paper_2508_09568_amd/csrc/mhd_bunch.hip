@@ -106,14 +106,16 @@ __global__ __launch_bounds__(BLK) void k_pred(const PatchDev* __restrict__ pt,
   }
 }
 
-// Where the two-phase tile lets 4 work-groups of 256 share a compute unit's 160 KB of LDS,
-// the waves-per-SIMD hint asks the register allocation to match (4 waves: <= 128 VGPRs).
+// Where the two-phase tile lets 16 waves (4 per SIMD) share a compute unit's 160 KB of LDS,
+// the waves-per-SIMD hint asks the register allocation to match (<= 128 VGPRs).
 template <typename T, int TX, int TY, int TZ, int SPLIT>
 struct SolveWaves {
-  static constexpr int value = (SPLIT && TileShape<TX, TY, TZ>::THREADS == 256 &&
-                                4 * TileShape<TX, TY, TZ>::LDS_SPLIT * (int)sizeof(T) <= 160 * 1024)
-                                   ? 4
-                                   : 1;
+  static constexpr int WG = TileShape<TX, TY, TZ>::THREADS / 64;  // waves per work-group
+  static constexpr int value =
+      (SPLIT && WG >= 4 && 16 % WG == 0 &&
+       (16 / WG) * TileShape<TX, TY, TZ>::LDS_SPLIT * (int)sizeof(T) <= 160 * 1024)
+          ? 4
+          : 1;
 };
 template <typename T, int TX, int TY, int TZ, int SPLIT>
 __global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS),
@@ -321,7 +323,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Solver tile shapes per activity pattern (bit d set = direction d active), the first one
 // the default.  The lists drive both the host-side tables and the kernel instantiations.
-#define MHD_SHAPES_7(F) F(8, 8, 4) F(16, 4, 4) F(8, 4, 8) F(16, 8, 2) F(32, 4, 2) F(8, 8, 2)
+#define MHD_SHAPES_7(F) \
+  F(8, 8, 4) F(16, 4, 4) F(8, 4, 8) F(16, 8, 2) F(32, 4, 2) F(8, 8, 2) F(32, 8, 2) F(32, 4, 4)
 #define MHD_SHAPES_3(F) F(16, 16, 1) F(32, 8, 1) F(64, 4, 1) F(8, 8, 1)
 #define MHD_SHAPES_1(F) F(64, 1, 1) F(128, 1, 1)
 #define MHD_SHAPES_6(F) F(1, 16, 16)
@@ -339,7 +342,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
     case 2: F(1, 128, 1) break;                \
     default: F(1, 1, 128) break;               \
   }
-constexpr int MAXSHAPE = 6;
+constexpr int MAXSHAPE = 8;
 constexpr int NMODE = 3;  // launch modes per tile shape: plain grid, XCD remap, persistent
 struct TileCand {
   int x, y, z;
@@ -1110,43 +1113,50 @@ mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* Uin, void* Uout, const d
   h->prof = false;
   hipEvent_t a = nullptr, b = nullptr;
   bool ok = h->hip_ok(hipEventCreate(&a), "autotune event") && h->hip_ok(hipEventCreate(&b), "autotune event");
-  int bi = 0;
-  float bms = 0.0f;
-  for (int k = 0; k < n && ok; ++k) {
-    h->shape = k / NMODE;
-    h->mode = k % NMODE;
-    ok = mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;  // warm-up
+  // mean time of `reps` updates after one warm-up, in the current configuration
+  auto time_it = [&](float* t) {
+    ok = ok && mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;
     ok = ok && h->hip_ok(hipEventRecord(a, s), "autotune event");
     for (int r = 0; r < reps && ok; ++r) ok = mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;
     ok = ok && h->hip_ok(hipEventRecord(b, s), "autotune event") &&
-         h->hip_ok(hipEventSynchronize(b), "autotune sync");
-    float t = 0.0f;
-    ok = ok && h->hip_ok(hipEventElapsedTime(&t, a, b), "autotune timing");
-    t /= reps;
-    if (ms) ms[k] = t;
-    if (ok && (k == 0 || t < bms)) {
-      bi = k;
-      bms = t;
+         h->hip_ok(hipEventSynchronize(b), "autotune sync") &&
+         h->hip_ok(hipEventElapsedTime(t, a, b), "autotune timing");
+    *t /= reps;
+  };
+  // tile shape x launch mode x solver form, jointly (the two-phase form is what lets the
+  // larger tiles fit), then the predictor form with the winner
+  int bi = 0, bsplit = 0;
+  float bms = 0.0f;
+  bool first = true;
+  for (int k = 0; k < n && ok; ++k) {
+    h->shape = k / NMODE;
+    h->mode = k % NMODE;
+    float kbest = 0.0f;
+    for (int sp = 0; sp < 2 && ok; ++sp) {
+      h->split = sp;
+      float t = 0.0f;
+      time_it(&t);
+      if (!ok) break;
+      if (sp == 0 || t < kbest) kbest = t;
+      if (first || t < bms) {
+        bi = k;
+        bsplit = sp;
+        bms = t;
+        first = false;
+      }
     }
+    if (ms) ms[k] = kbest;
   }
   h->shape = bi / NMODE;
   h->mode = bi % NMODE;
-  // then, with that configuration, the two-phase solver tile and the fused predictor
-  int* knob[2] = {&h->split, &h->fused};
-  for (int q = 0; q < 2 && ok; ++q) {
-    const int v0 = *knob[q];
-    float kms[2] = {0.0f, 0.0f};
-    for (int f = 0; f < 2 && ok; ++f) {
-      *knob[q] = f;
-      ok = mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;
-      ok = ok && h->hip_ok(hipEventRecord(a, s), "autotune event");
-      for (int r = 0; r < reps && ok; ++r) ok = mhd_bunch_update(h, Uin, Uout, dt, dx, s) == MHD_OK;
-      ok = ok && h->hip_ok(hipEventRecord(b, s), "autotune event") &&
-           h->hip_ok(hipEventSynchronize(b), "autotune sync") &&
-           h->hip_ok(hipEventElapsedTime(&kms[f], a, b), "autotune timing");
-    }
-    *knob[q] = ok ? (kms[1] < kms[0] ? 1 : 0) : v0;
+  h->split = bsplit;
+  const int f0 = h->fused;
+  float fms[2] = {0.0f, 0.0f};
+  for (int f = 0; f < 2 && ok; ++f) {
+    h->fused = f;
+    time_it(&fms[f]);
   }
+  h->fused = ok ? (fms[1] < fms[0] ? 1 : 0) : f0;
   if (a) (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
   h->prof = prof;
