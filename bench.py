@@ -26,7 +26,7 @@ import time
 METRIC = "MHD cell-updates/s and % HBM roofline, FP64/FP32, batched vs per-bunch"
 PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TFLOPS = {8: 78.6, 4: 157.3}     # MI355X vector FP64 / FP32 (published)
-UPDATE_KERNELS = ("prim", "edge_emf_n", "predict", "solve")
+UPDATE_KERNELS = ("prim", "edge_emf_n", "predict", "edge", "solve")
 
 
 def log(*a):
@@ -347,8 +347,8 @@ def main():
                     help="use this launch configuration instead of autotuning")
     ap.add_argument("--predictor", type=int, default=None, choices=(0, 1),
                     help="force the staged (0) or fused (1) predictor")
-    ap.add_argument("--split", type=int, default=None, choices=(0, 1),
-                    help="force the one- (0) or two-phase (1) solver tile")
+    ap.add_argument("--split", type=int, default=None, choices=(0, 1, 2),
+                    help="force the solver form: one-phase (0), two-phase (1), edge pass (2)")
     ap.add_argument("--fp32-only", action="store_true",
                     help="skip the FP64 run (profiling of the FP32 kernels)")
     ap.add_argument("--batched-steps", type=int, default=10)

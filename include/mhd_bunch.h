@@ -156,14 +156,16 @@ mhd_status mhd_bunch_tile_set(mhd_bunch* h, int32_t index);
 mhd_status mhd_bunch_set_predictor(mhd_bunch* h, int32_t fused);
 int32_t mhd_bunch_predictor(const mhd_bunch* h);
 
-/* Solver tile: 0 = face fluxes and edge EMFs of the tile held in shared memory together, then
- * the whole update; 1 = two phases (face fluxes, hydro update; then edge EMFs, field update)
- * that share the shared memory, for more work-groups per compute unit.  Same values either
- * way.  Default 0. */
+/* Solver form: 0 = face fluxes and edge EMFs of the tile held in shared memory together,
+ * then the whole update; 1 = two phases (face fluxes, hydro update; then edge EMFs, field
+ * update) that share the shared memory, for more work-groups per compute unit; 2 = a
+ * separate pass computes every edge EMF once into the workspace scratch and the tile does
+ * the face fluxes and the update (no halo edges recomputed).  Same values in every form.
+ * Default 0. */
 mhd_status mhd_bunch_set_solver_split(mhd_bunch* h, int32_t split);
 int32_t mhd_bunch_solver_split(const mhd_bunch* h);
 
-/* Times every configuration, each with both solver-tile forms, on the caller's data (one
+/* Times every configuration, each with every solver form, on the caller's data (one
  * warm-up and `reps` timed updates of U_in -> U_out each, HIP events on `stream`) and keeps
  * the fastest pair; then, with it, times both predictor forms and keeps the faster.
  * Synchronises `stream`; overwrites U_out.  best (may be NULL) receives the chosen
@@ -202,10 +204,11 @@ enum {
   MHD_KERNEL_PRIM = 0,        /* primitives */
   MHD_KERNEL_EDGE_EMF_N = 1,  /* edge EMFs at time n */
   MHD_KERNEL_PREDICT = 2,     /* slopes, half-step state and face field */
-  MHD_KERNEL_SOLVE = 3,       /* HLLD fluxes, edge EMFs, update */
+  MHD_KERNEL_SOLVE = 3,       /* HLLD fluxes, edge EMFs (forms 0, 1), update */
   MHD_KERNEL_CFL = 4,         /* time step (three small kernels, timed together) */
   MHD_KERNEL_GUARDS = 5,      /* guard fill */
-  MHD_KERNEL_COUNT = 6
+  MHD_KERNEL_EDGE = 6,        /* half-step edge EMFs (solver form 2) */
+  MHD_KERNEL_COUNT = 7
 };
 mhd_status mhd_bunch_profile(mhd_bunch* h, int32_t enable);
 mhd_status mhd_bunch_profile_read(mhd_bunch* h, int32_t kernel, double* total_ms, int64_t* launches);

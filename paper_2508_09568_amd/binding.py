@@ -99,7 +99,8 @@ _SIGS = {
     "mhd_bunch_solver_split": (C.c_int32, [_h]),
 }
 
-KERNELS = {"prim": 0, "edge_emf_n": 1, "predict": 2, "solve": 3, "cfl": 4, "guards": 5}
+KERNELS = {"prim": 0, "edge_emf_n": 1, "predict": 2, "solve": 3, "cfl": 4, "guards": 5,
+           "edge": 6}
 
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -265,8 +266,9 @@ class Bunch:
     def predictor(self):
         return int(mhd_bunch_predictor(self._h))
 
-    def set_solver_split(self, split):
-        _ok(mhd_bunch_set_solver_split(self._h, int(bool(split))), "mhd_bunch_set_solver_split")
+    def set_solver_split(self, form):
+        """Solver form: 0 one-phase tile, 1 two-phase tile, 2 separate edge-EMF pass."""
+        _ok(mhd_bunch_set_solver_split(self._h, int(form)), "mhd_bunch_set_solver_split")
 
     def solver_split(self):
         return int(mhd_bunch_solver_split(self._h))

@@ -108,28 +108,28 @@ __global__ __launch_bounds__(BLK) void k_pred(const PatchDev* __restrict__ pt,
 
 // Where the two-phase tile lets 16 waves (4 per SIMD) share a compute unit's 160 KB of LDS,
 // the waves-per-SIMD hint asks the register allocation to match (<= 128 VGPRs).
-template <typename T, int TX, int TY, int TZ, int SPLIT>
+template <typename T, int TX, int TY, int TZ, int FORM>
 struct SolveWaves {
   static constexpr int WG = TileShape<TX, TY, TZ>::THREADS / 64;  // waves per work-group
   static constexpr int value =
-      (SPLIT && WG >= 4 && 16 % WG == 0 &&
-       (16 / WG) * TileShape<TX, TY, TZ>::LDS_SPLIT * (int)sizeof(T) <= 160 * 1024)
+      (FORM != 0 && WG >= 4 && 16 % WG == 0 &&
+       (16 / WG) * TileShape<TX, TY, TZ>::template Lds<FORM>::value * (int)sizeof(T) <= 160 * 1024)
           ? 4
           : 1;
 };
-template <typename T, int TX, int TY, int TZ, int SPLIT>
+template <typename T, int TX, int TY, int TZ, int FORM>
 __global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS),
-                             (SolveWaves<T, TX, TY, TZ, SPLIT>::value)) void k_solve(
+                             (SolveWaves<T, TX, TY, TZ, FORM>::value)) void k_solve(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, const T* __restrict__ Uin,
     T* __restrict__ Uout, const T* __restrict__ S, const double* __restrict__ dt,
     const double* __restrict__ dx, Consts<T> c, int g, int ntile, int remap) {
-  __shared__ T lds[SPLIT ? TileShape<TX, TY, TZ>::LDS_SPLIT : TileShape<TX, TY, TZ>::LDS_ELEMS];
+  __shared__ T lds[TileShape<TX, TY, TZ>::template Lds<FORM>::value];
   DevX ex;
   for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
     const TileDev tl = tiles[logical_block(vb, ntile, remap)];
     const PatchDev& P = pt[tl.patch];
-    solve_tile<T, TX, TY, TZ, SPLIT>(ex, lds, P, g, tl, Uin, Uout, S, dt[tl.patch],
-                                     dx + 3 * tl.patch, c);
+    solve_tile<T, TX, TY, TZ, FORM>(ex, lds, P, g, tl, Uin, Uout, S, dt[tl.patch],
+                                    dx + 3 * tl.patch, c);
     ex.sync();  // the next tile reuses the shared memory
   }
 }
@@ -152,6 +152,20 @@ __global__ __launch_bounds__((PredShape<PX, PY, PZ>::THREADS),
     ex.sync();  // the next tile reuses the shared memory
   }
   if (bad) atomicOr(status, 1);
+}
+
+// half-step edge EMFs, each edge once, by the solver tiles that own them (solver form 2)
+template <typename T, int TX, int TY, int TZ>
+__global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS)) void k_edges(
+    const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, T* __restrict__ S,
+    const double* __restrict__ dx, Consts<T> c, int g, int ntile, int remap) {
+  DevX ex;
+  for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
+    const TileDev tl = tiles[logical_block(vb, ntile, remap)];
+    const PatchDev& P = pt[tl.patch];
+    solve_tile<T, TX, TY, TZ, 3>(ex, (T*)nullptr, P, g, tl, (const T*)S, S, S, 1.0, dx + 3 * tl.patch,
+                                 c);
+  }
 }
 
 template <typename T>
@@ -376,7 +390,7 @@ struct mhd_bunch {
   std::vector<TileDev> tiles[MAXSHAPE];
   // fused predictor (mhd_bunch_set_predictor): tile table over the predictor boxes
   int fused = 0;
-  int split = 0;  // two-phase solver tile (mhd_bunch_set_solver_split)
+  int split = 0;  // solver form (mhd_bunch_set_solver_split): 0 one-phase, 1 two-phase, 2 edge pass
   int PXs = 8, PYs = 8, PZs = 4;
   std::vector<TileDev> ptiles;
   size_t o_ptiles = 0;
@@ -495,32 +509,54 @@ void set_shapes(mhd_bunch* h) {
 #undef MHD_ADD
 }
 
-template <typename T, int X, int Y, int Z, int SPLIT>
+template <typename T, int X, int Y, int Z, int FORM>
 void solve_launch(mhd_bunch* h, int nt, const TileDev* tl, const T* Uin, T* Uout, const T* S,
                   const double* dt, const double* dx, const Consts<T>& c, hipStream_t s) {
   int grid = nt;
   if (h->mode == 2) {
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void*>(k_solve<T, X, Y, Z, SPLIT>),
+            &occ, reinterpret_cast<const void*>(k_solve<T, X, Y, Z, FORM>),
             TileShape<X, Y, Z>::THREADS, 0) != hipSuccess || occ < 1)
       occ = 1;
     grid = h->persistent_grid(nt, occ);
   }
-  hipLaunchKernelGGL((k_solve<T, X, Y, Z, SPLIT>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0,
+  hipLaunchKernelGGL((k_solve<T, X, Y, Z, FORM>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0,
                      s, h->d_pt(), tl, Uin, Uout, S, dt, dx, c, h->g, nt, h->mode >= 1);
 }
 
+template <typename T, int X, int Y, int Z>
+void edges_launch(mhd_bunch* h, int nt, const TileDev* tl, T* S, const double* dx,
+                  const Consts<T>& c, hipStream_t s) {
+  int grid = nt;
+  if (h->mode == 2) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, reinterpret_cast<const void*>(k_edges<T, X, Y, Z>), TileShape<X, Y, Z>::THREADS,
+            0) != hipSuccess || occ < 1)
+      occ = 1;
+    grid = h->persistent_grid(nt, occ);
+  }
+  hipLaunchKernelGGL((k_edges<T, X, Y, Z>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0, s,
+                     h->d_pt(), tl, S, dx, c, h->g, nt, h->mode >= 1);
+}
+
+// edges = true: the owned-edge pass of solver form 2; else the solver tiles
 template <typename T>
-void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uout, const T* S,
-                  const double* dt, const double* dx, const Consts<T>& c, hipStream_t s) {
+void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uout, T* S,
+                  const double* dt, const double* dx, const Consts<T>& c, hipStream_t s,
+                  bool edges) {
   const int k = h->shape;
   const TileCand tc = h->shapes[k];
   const int nt = ch.ntile[k];
   const TileDev* tl = h->d_tiles(k) + ch.tile0[k];
 #define MHD_TRY(X, Y, Z)                                                                      \
   if (tc.x == X && tc.y == Y && tc.z == Z) {                                                  \
-    if (h->split)                                                                             \
+    if (edges)                                                                                \
+      edges_launch<T, X, Y, Z>(h, nt, tl, S, dx, c, s);                                       \
+    else if (h->split == 2)                                                                   \
+      solve_launch<T, X, Y, Z, 2>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                    \
+    else if (h->split == 1)                                                                   \
       solve_launch<T, X, Y, Z, 1>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                    \
     else                                                                                      \
       solve_launch<T, X, Y, Z, 0>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                    \
@@ -590,9 +626,14 @@ mhd_status launch_update(mhd_bunch* h, const T* Uin, T* Uout, const double* dt, 
                          h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], Uin, S, dt, dx, c, h->g, nb, rm);
       h->toc(s, MHD_KERNEL_PREDICT, t0);
     }
+    if (h->split == 2 && ch.ntile[h->shape]) {
+      t0 = h->tic(s);
+      launch_solve<T>(h, ch, Uin, Uout, S, dt, dx, c, s, true);
+      h->toc(s, MHD_KERNEL_EDGE, t0);
+    }
     if (ch.ntile[h->shape]) {
       t0 = h->tic(s);
-      launch_solve<T>(h, ch, Uin, Uout, (const T*)S, dt, dx, c, s);
+      launch_solve<T>(h, ch, Uin, Uout, S, dt, dx, c, s, false);
       h->toc(s, MHD_KERNEL_SOLVE, t0);
     }
   }
@@ -1096,7 +1137,7 @@ mhd_status mhd_bunch_set_predictor(mhd_bunch* h, int32_t fused) {
 int32_t mhd_bunch_predictor(const mhd_bunch* h) { return h ? h->fused : -1; }
 
 mhd_status mhd_bunch_set_solver_split(mhd_bunch* h, int32_t split) {
-  if (!h || (split != 0 && split != 1)) return MHD_EINVAL;
+  if (!h || split < 0 || split > 2) return MHD_EINVAL;
   h->split = split;
   return MHD_OK;
 }
@@ -1123,8 +1164,8 @@ mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* Uin, void* Uout, const d
          h->hip_ok(hipEventElapsedTime(t, a, b), "autotune timing");
     *t /= reps;
   };
-  // tile shape x launch mode x solver form, jointly (the two-phase form is what lets the
-  // larger tiles fit), then the predictor form with the winner
+  // tile shape x launch mode x solver form, jointly (the two-phase and edge-pass forms are
+  // what let the larger tiles fit), then the predictor form with the winner
   int bi = 0, bsplit = 0;
   float bms = 0.0f;
   bool first = true;
@@ -1132,7 +1173,7 @@ mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* Uin, void* Uout, const d
     h->shape = k / NMODE;
     h->mode = k % NMODE;
     float kbest = 0.0f;
-    for (int sp = 0; sp < 2 && ok; ++sp) {
+    for (int sp = 0; sp < 3 && ok; ++sp) {
       h->split = sp;
       float t = 0.0f;
       time_it(&t);

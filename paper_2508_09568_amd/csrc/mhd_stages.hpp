@@ -809,11 +809,21 @@ struct TileShape {
   // arrays take turns in the same shared memory
   static constexpr int NFLUX = 5 * (NFX + NFY + NFZ), NEMF = NEZ + NEX + NEY;
   static constexpr int LDS_SPLIT = NFLUX > NEMF ? NFLUX : NEMF;
+  template <int FORM>
+  struct Lds {
+    static constexpr int value = FORM == 0 ? LDS_ELEMS : (FORM == 1 ? LDS_SPLIT : NFLUX);
+  };
   static constexpr int THREADS = TX * TY * TZ < 64 ? 64 : TX * TY * TZ;
   static_assert(THREADS % 64 == 0, "solver work-groups are whole wavefronts");
 };
 
-template <typename T, int TX, int TY, int TZ, int SPLIT, class X>
+// FORM 0: face fluxes and edge EMFs of the tile in shared memory together, then the update;
+// FORM 1: two phases (faces and hydro update, then edges and field update) sharing the
+// shared memory; FORM 2: faces only, the half-step edge EMFs having been computed once per
+// edge by a FORM 3 pass into the scratch slots of the time-n EMFs (P.sbase + (8 + e) Nc);
+// FORM 3: that pass -- the edges the tile owns (its cells' lower edges, plus the upper layer
+// where the tile ends the patch), written to the scratch, no update.
+template <typename T, int TX, int TY, int TZ, int FORM, class X>
 __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDev& P, int g,
                                                     const TileDev& tl, const T* Uin, T* Uout,
                                                     const T* Win, double dt, const double* dxp,
@@ -822,6 +832,7 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
   T* fx = lds;
   T* fy = fx + 5 * SH::NFX;
   T* fz = fy + 5 * SH::NFY;
+  constexpr int SPLIT = FORM == 1, EXT = FORM == 2, EDGES = FORM == 3;
   T* ez = SPLIT ? lds : fz + 5 * SH::NFZ;
   T* exx = ez + SH::NEZ;
   T* ey = exx + SH::NEX;
@@ -851,14 +862,36 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
                 B5 = B4 + (NS[4] + WAVE - 1) / WAVE * WAVE, B6 = B5 + (NS[5] + WAVE - 1) / WAVE * WAVE;
   const int fact[3] = {ax, ay, az};
   const T dtdx[3] = {T(dt / dxp[0]), T(dt / dxp[1]), T(dt / dxp[2])};
+  // external EMFs: E_e of padded cell (i, j, k) at Win[P.sbase + (8 + e) Nc + cell]
+  const T* eg = Win + P.sbase + 8 * P.Nc;
   const int ncell = tx * ty * tz;
   const int64_t Nc = P.Nc;
   const T* u = Uin + P.ubase;
   T* uo = Uout + P.ubase;
 
   for (int phase = 0; phase < (SPLIT ? 2 : 1); ++phase) {
+    if (EDGES) {
+      // the owned edges only; no shared memory, no update
+      for (int it = B3 + tid; it < B6; it += nth) {
+        const int k = wave_uniform(it < B4 ? 3 : it < B5 ? 4 : 5);
+        int lx, ly, lz;
+        switch (k) {
+          case 3: { const int r = it - B3; lx = r % TX; ly = (r / TX) % Y1; lz = r / (TX * Y1); break; }
+          case 4: { const int r = it - B4; lx = r % X1; ly = (r / X1) % TY; lz = r / (X1 * TY); break; }
+          default: { const int r = it - B5; lx = r % X1; ly = (r / X1) % Y1; lz = r / (X1 * Y1); break; }
+        }
+        const int e = k - 3;
+        const int e0 = tx + (e != 0 && ax && tl.x0 + tx == P.n[0]);
+        const int e1 = ty + (e != 1 && ay && tl.y0 + ty == P.n[1]);
+        const int e2 = tz + (e != 2 && az && tl.z0 + tz == P.n[2]);
+        if (lx >= e0 || ly >= e1 || lz >= e2) continue;
+        const int64_t cg = cell_of(P, i0 + lx, j0 + ly, k0 + lz);
+        const_cast<T*>(eg)[e * Nc + cg] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
+      }
+      return;
+    }
     const int ibeg = SPLIT && phase == 1 ? B3 : 0;
-    const int iend = SPLIT && phase == 0 ? B3 : B6;
+    const int iend = (SPLIT && phase == 0) || EXT ? B3 : B6;
     for (int it = ibeg + tid; it < iend; it += nth) {
       const int k = wave_uniform(it < B1 ? 0 : it < B2 ? 1 : it < B3 ? 2 : it < B4 ? 3 : it < B5 ? 4 : 5);
       int lx, ly, lz, e0, e1, e2;
@@ -890,7 +923,7 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         fd[(1 + a) * NF + li] = F[2];
         fd[(1 + b) * NF + li] = F[3];
         fd[4 * NF + li] = F[4];
-      } else {
+      } else if (!EXT) {
         // edge along e: extents t + 1 along the two transverse directions when active
         const int e = k - 3;
         e0 = tx + (e != 0 && ax);
@@ -918,7 +951,22 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
           uo[m * Nc + cell] = v;
         }
       }
-      if (!SPLIT || phase == 1) {
+      if (EXT) {
+        const int64_t ox = P.off[0], oy = P.off[1], oz = P.off[2];
+        const T* E0 = eg;
+        const T* E1 = eg + Nc;
+        const T* E2 = eg + 2 * Nc;
+        T bx = u[5 * Nc + cell], by = u[6 * Nc + cell], bz = u[7 * Nc + cell];
+        if (ay) bx = bx + dtdx[1] * (E2[cell + oy] - E2[cell]);
+        if (az) bx = bx - dtdx[2] * (E1[cell + oz] - E1[cell]);
+        if (az) by = by + dtdx[2] * (E0[cell + oz] - E0[cell]);
+        if (ax) by = by - dtdx[0] * (E2[cell + ox] - E2[cell]);
+        if (ax) bz = bz + dtdx[0] * (E1[cell + ox] - E1[cell]);
+        if (ay) bz = bz - dtdx[1] * (E0[cell + oy] - E0[cell]);
+        uo[5 * Nc + cell] = bx;
+        uo[6 * Nc + cell] = by;
+        uo[7 * Nc + cell] = bz;
+      } else if (!SPLIT || phase == 1) {
         // edge arrays: ez (TX+1)x(TY+1)xTZ, ex TXx(TY+1)x(TZ+1), ey (TX+1)xTYx(TZ+1)
         const int zl = lx + (TX + 1) * (ly + (TY + 1) * lz);
         const int xl = lx + TX * (ly + (TY + 1) * lz);

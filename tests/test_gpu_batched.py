@@ -41,7 +41,7 @@ def test_every_launch_configuration_gives_identical_bits(case):
     for fused in (0, 1):
         B.set_predictor(fused)
         assert B.predictor() == fused
-        for split in (0, 1):
+        for split in (0, 1, 2):
             B.set_solver_split(split)
             assert B.solver_split() == split
             for i, cfg in enumerate(cfgs):
