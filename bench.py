@@ -35,14 +35,16 @@ def log(*a):
 
 # HBM bytes of one FP64 update (every update kernel), measured with rocprofv3 --pmc FETCH_SIZE
 # and WRITE_SIZE on the turbulence workload and scaled by the same counters on a plain
-# 1 GiB device copy (FETCH_SIZE reads 0.5x there, WRITE_SIZE 1x); see profiles/.  Valid only
-# for the kernel sources it was measured on: reported as null once they change.
+# 1 GiB device copy (FETCH_SIZE reads 0.5x there, WRITE_SIZE 1x); see profiles/.  Keyed by
+# launch configuration ((tile x, y, z, mode), fused predictor, solver form); valid only for
+# the kernel sources it was measured on: reported as null once they change.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "2ed2778b7bba8a42e63e1be0e5f98932b9d73125ecb252ba220bfbdaa3b41c10",
-    "tile": [32, 4, 2, 1],
-    "fused_predictor": 1,
-    "solver_split": 0,
-    "bytes_per_update": 1.8422e11,
+    "sources_sha256": "b437349a37f4aa3f29675ad57a82f8c200d714eb9fba66a768f057e77cf80525",
+    "bytes_per_update": {
+        "[32, 4, 2, 1]/1/0": 183.98e9,
+        "[32, 4, 4, 1]/1/1": 227.79e9,
+        "[32, 8, 2, 1]/1/1": 229.44e9,
+    },
     "profile": "profiles/mhd_update_turbulence512_pmc.md",
 }
 
@@ -59,10 +61,9 @@ def kernel_sources_sha256():
 
 def measured_traffic(tile, fused, split):
     m = MEASURED_TRAFFIC
-    if m["sources_sha256"] != kernel_sources_sha256() or m.get("tile") != list(tile) or \
-            m.get("fused_predictor") != fused or m.get("solver_split") != split:
+    if m["sources_sha256"] != kernel_sources_sha256():
         return None
-    return m["bytes_per_update"]
+    return m["bytes_per_update"].get(f"{list(tile)}/{fused}/{split}")
 
 
 def algorithmic_bytes_per_cell(n, g, s):
