@@ -66,6 +66,21 @@ __host__ __device__ __forceinline__ double m_sqrt(double x) {
   return sqrt(x);
 #endif
 }
+// square root of a strictly positive finite argument (no zero guard)
+__host__ __device__ __forceinline__ float m_sqrt_pos(float x) { return m_sqrt(x); }
+__host__ __device__ __forceinline__ double m_sqrt_pos(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  return fma(h, d, g);
+#else
+  return sqrt(x);
+#endif
+}
 __host__ __device__ __forceinline__ float m_rsqrt(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __builtin_amdgcn_rsqf(x);
@@ -131,6 +146,11 @@ __host__ __device__ __forceinline__ Dual<T> m_sqrt(Dual<T> x) {
   return Dual<T>(s, x.d * (T(0.5) * m_rcp(s)));
 }
 template <typename T>
+__host__ __device__ __forceinline__ Dual<T> m_sqrt_pos(Dual<T> x) {
+  const T s = m_sqrt_pos(x.v);
+  return Dual<T>(s, x.d * (T(0.5) * m_rcp(s)));
+}
+template <typename T>
 __host__ __device__ __forceinline__ Dual<T> m_rsqrt(Dual<T> x) {
   const T y = m_rsqrt(x.v);
   return Dual<T>(y, (T(-0.5) * x.d) * (y * y * y));
@@ -193,10 +213,11 @@ __host__ __device__ __forceinline__ WaveBase<T> wave_base(T rho, T p, T bsq, T g
   w.d2 = d * d;
   return w;
 }
+// (the outer argument is at least a^2 > 0: pressure and density are floored positive)
 template <typename T>
 __host__ __device__ __forceinline__ T fast_speed_t(const WaveBase<T>& w, T bt) {
   const T rad = w.d2 + T(4) * w.a2 * (bt * w.ir);
-  return m_sqrt(T(0.5) * (w.a2 + w.b2 + m_sqrt(rad)));
+  return m_sqrt_pos(T(0.5) * (w.a2 + w.b2 + m_sqrt(rad)));
 }
 template <typename T>
 __host__ __device__ __forceinline__ T fast_speed(T rho, T p, T bn, T bt1, T bt2, T gamma) {
@@ -310,24 +331,32 @@ __host__ __device__ __forceinline__ void hlld_flux(const T s[2][7], T bn, const 
   else if (Ss[1] >= T(0)) reg = 3;
   else if (S[1] >= T(0)) reg = 4;
   else reg = 5;
-  const int k = reg <= 2 ? 0 : 1;
-  const T r = s[k][0], u = s[k][1], v = s[k][2], w = s[k][3];
-  const T by = s[k][5], bz = s[k][6];
+  // the side of the contact: every per-side quantity is picked by a two-way select (a run-time
+  // index into the 2 x 7 state array would become a select chain over all 14 entries)
+  const bool lft = reg <= 2;
+  const auto pick = [lft](T a, T b) { return lft ? a : b; };
+  const T r = pick(s[0][0], s[1][0]), u = pick(s[0][1], s[1][1]), v = pick(s[0][2], s[1][2]),
+          w = pick(s[0][3], s[1][3]);
+  const T by = pick(s[0][5], s[1][5]), bz = pick(s[0][6], s[1][6]);
+  const T ptk = pick(pt[0], pt[1]), enk = pick(en[0], en[1]), ubk = pick(ub[0], ub[1]);
   F[0] = r * u;
-  F[1] = r * u * u + pt[k] - bn2;
+  F[1] = r * u * u + ptk - bn2;
   F[2] = r * v * u - by * bn;
   F[3] = r * w * u - bz * bn;
-  F[4] = u * (en[k] + pt[k]) - bn * ub[k];
+  F[4] = u * (enk + ptk) - bn * ubk;
   if (reg >= 1 && reg <= 4) {
-    const T Us[5] = {rs[k], rs[k] * sm, rs[k] * vs[k], rs[k] * ws[k], es[k]};
-    const T Uo[5] = {r, r * u, r * v, r * w, en[k]};
+    const T rsk = pick(rs[0], rs[1]), esk = pick(es[0], es[1]);
+    const T Us[5] = {rsk, rsk * sm, rsk * pick(vs[0], vs[1]), rsk * pick(ws[0], ws[1]), esk};
+    const T Uo[5] = {r, r * u, r * v, r * w, enk};
+    const T Sk = pick(S[0], S[1]);
     T Fs[5];
-    for (int m = 0; m < 5; ++m) Fs[m] = F[m] + S[k] * (Us[m] - Uo[m]);
+    for (int m = 0; m < 5; ++m) Fs[m] = F[m] + Sk * (Us[m] - Uo[m]);
     if (reg == 2 || reg == 3) {
-      const T ess = k == 0 ? es[0] - sq[0] * (ubs[0] - ubss) * sg
-                           : es[1] + sq[1] * (ubs[1] - ubss) * sg;
-      const T Uss[5] = {rs[k], rs[k] * sm, rs[k] * vss, rs[k] * wss, ess};
-      for (int m = 0; m < 5; ++m) Fs[m] = Fs[m] + Ss[k] * (Uss[m] - Us[m]);
+      const T ess = lft ? es[0] - sq[0] * (ubs[0] - ubss) * sg
+                        : es[1] + sq[1] * (ubs[1] - ubss) * sg;
+      const T Uss[5] = {rsk, rsk * sm, rsk * vss, rsk * wss, ess};
+      const T Ssk = pick(Ss[0], Ss[1]);
+      for (int m = 0; m < 5; ++m) Fs[m] = Fs[m] + Ssk * (Uss[m] - Us[m]);
     }
     for (int m = 0; m < 5; ++m) F[m] = Fs[m];
   }

@@ -229,11 +229,13 @@ __host__ __device__ __forceinline__ S e_at(const EnOnTheFly<S, AQ, AU>& e, int c
 // The 38 predictor values of padded cell (i, j, k): q + dt/2 dq/dt, limited slopes, half-step
 // field on the three lower faces, transverse slopes of those face fields.  q reads the
 // primitives, e the edge EMFs (absolute index P.sbase + 8 Nc + e Nc + cell), u reads U.
-template <typename S, class AU, class AQ, class AE>
+// w receives value v by `w[v] = x`: an array of NW, or a WStore that writes it to the W block
+// at once (no value is read back).
+template <typename S, class AU, class AQ, class AE, class WO>
 __host__ __device__ __forceinline__ void pred_point(const PatchDev& P, int i, int j, int k,
                                                     const AU& u, const AQ& q, const AE& e,
                                                     double dt, const double* dxp,
-                                                    const Consts<S>& c, S w[NW]) {
+                                                    const Consts<S>& c, WO&& w) {
   const int64_t Nc = P.Nc;
   const int64_t cell = cell_of(P, i, j, k);
   const int64_t qb = P.sbase + cell, ub = P.ubase + cell, eb = P.sbase + 8 * Nc + cell;
@@ -367,13 +369,23 @@ __host__ __device__ __forceinline__ S edge_point(const PatchDev& P, int g, int e
 }
 
 // ------------------------------------------------ forward writers of stages 1-3
-// the NW predictor values of one cell into the patch's predictor block (32-bit offsets)
+// Writes predictor value v of one cell straight into the patch's predictor block (base of the
+// block, 32-bit offsets), so a value's registers are free once it is computed.
 template <typename T>
-__host__ __device__ __forceinline__ void store_w(T* base, uint32_t wcell, uint32_t Nw,
-                                                 const T w[NW]) {
-  char* b = reinterpret_cast<char*>(base);
-  for (int v = 0; v < NW; ++v)
-    *reinterpret_cast<T*>(b + (uint32_t)((wcell + (uint32_t)v * Nw) * (uint32_t)sizeof(T))) = w[v];
+struct WStore {
+  char* b;
+  uint32_t wcell, Nw;
+  struct Ref {
+    T* p;
+    __host__ __device__ __forceinline__ void operator=(T x) const { *p = x; }
+  };
+  __host__ __device__ __forceinline__ Ref operator[](int v) const {
+    return Ref{reinterpret_cast<T*>(b + (uint32_t)((wcell + (uint32_t)v * Nw) * (uint32_t)sizeof(T)))};
+  }
+};
+template <typename T>
+__host__ __device__ __forceinline__ WStore<T> w_store(T* base, uint32_t wcell, uint32_t Nw) {
+  return WStore<T>{reinterpret_cast<char*>(base), wcell, Nw};
 }
 
 template <typename T>
@@ -398,9 +410,8 @@ template <typename T>
 __host__ __device__ __forceinline__ void pred_item(const PatchDev& P, int g, int i, int j, int k,
                                                    const T* U, const T* S, T* Wout, double dt,
                                                    const double* dxp, const Consts<T>& c) {
-  T w[NW];
-  pred_point(P, i, j, k, Ld<T>{U}, Ld<T>{S}, Ld<T>{S}, dt, dxp, c, w);
-  store_w(Wout + P.wbase, (uint32_t)wcell_of(P, g, i, j, k), (uint32_t)P.Nwc, w);
+  pred_point(P, i, j, k, Ld<T>{U}, Ld<T>{S}, Ld<T>{S}, dt, dxp, c,
+             w_store(Wout + P.wbase, (uint32_t)wcell_of(P, g, i, j, k), (uint32_t)P.Nwc));
 }
 
 template <typename T>
@@ -725,15 +736,23 @@ struct PredShape {
   static constexpr int THREADS = PX * PY * PZ < 64 ? 64 : PX * PY * PZ;
 };
 
+// The tile shape follows the bunch's activity pattern (direction d is active exactly when the
+// tile extent along d exceeds 1), so the local box and its strides are compile-time constants
+// (shared-memory offsets fold into the instructions); a ragged tile at the end of the box uses
+// the leading part of the local box.
 template <typename T, int PX, int PY, int PZ, class X>
 __host__ __device__ __forceinline__ int predict_tile(X& ex, T* L, const PatchDev& P, int g,
                                                      const TileDev& tl, const T* U, T* W,
                                                      double dt, const double* dxp,
                                                      const Consts<T>& c) {
-  const int PT[3] = {PX, PY, PZ}, t0[3] = {tl.x0, tl.y0, tl.z0};
+  using SH = PredShape<PX, PY, PZ>;
+  constexpr int PT[3] = {PX, PY, PZ}, LB[3] = {SH::LX, SH::LY, SH::LZ};
+  constexpr int64_t Nl = SH::NL;
+  const int t0[3] = {tl.x0, tl.y0, tl.z0};
   int e3[3], o3[3], l3[3];  // tile extent, padded index of its first cell, local box extent
+  #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    if (active(P, d)) {
+    if (PT[d] > 1) {
       e3[d] = P.n[d] + 2 - t0[d] < PT[d] ? P.n[d] + 2 - t0[d] : PT[d];
       o3[d] = g - 1 + t0[d];
       l3[d] = e3[d] + 2;
@@ -744,23 +763,24 @@ __host__ __device__ __forceinline__ int predict_tile(X& ex, T* L, const PatchDev
     }
   }
   PatchDev F = {};
-  F.act = P.act;
-  for (int d = 0; d < 3; ++d) F.N[d] = l3[d];
-  F.Nc = (int64_t)l3[0] * l3[1] * l3[2];
-  F.off[0] = active(P, 0) ? 1 : 0;
-  F.off[1] = active(P, 1) ? l3[0] : 0;
-  F.off[2] = active(P, 2) ? (int64_t)l3[0] * l3[1] : 0;
+  F.act = (PX > 1) | (PY > 1) << 1 | (PZ > 1) << 2;
+  #pragma unroll
+  for (int d = 0; d < 3; ++d) F.N[d] = LB[d];
+  F.Nc = Nl;
+  F.off[0] = PX > 1 ? 1 : 0;
+  F.off[1] = PY > 1 ? LB[0] : 0;
+  F.off[2] = PZ > 1 ? LB[0] * LB[1] : 0;
   F.sbase = 0;
-  F.ubase = 3 * F.Nc;
-  const int64_t Nl = F.Nc;
+  F.ubase = 3 * Nl;
   const int tid = ex.tid(), nth = ex.nthr();
   int bad = 0;
   // 1. primitives and face fields of the local box (local index 0 = one cell below the tile)
   for (int it = tid; it < Nl; it += nth) {
-    const int li = it % l3[0], lj = (it / l3[0]) % l3[1], lk = it / (l3[0] * l3[1]);
-    const int gi = active(P, 0) ? o3[0] - 1 + li : 0;
-    const int gj = active(P, 1) ? o3[1] - 1 + lj : 0;
-    const int gk = active(P, 2) ? o3[2] - 1 + lk : 0;
+    const int li = it % LB[0], lj = (it / LB[0]) % LB[1], lk = it / (LB[0] * LB[1]);
+    if (li >= l3[0] || lj >= l3[1] || lk >= l3[2]) continue;
+    const int gi = PX > 1 ? o3[0] - 1 + li : 0;
+    const int gj = PY > 1 ? o3[1] - 1 + lj : 0;
+    const int gk = PZ > 1 ? o3[2] - 1 + lk : 0;
     const int64_t gc = cell_of(P, gi, gj, gk);
     T q[8];
     bad |= prim_point(P, gc, Ld<T>{U}, c, q);
@@ -769,19 +789,17 @@ __host__ __device__ __forceinline__ int predict_tile(X& ex, T* L, const PatchDev
   }
   ex.sync();
   // 2. predictor values of the tile's cells (local [1, e + 1) in active directions)
-  int lo3[3];
-  for (int d = 0; d < 3; ++d) lo3[d] = active(P, d) ? 1 : 0;
+  constexpr int lo3[3] = {PX > 1, PY > 1, PZ > 1};
   const Ld<T> lq{L};
   const EnOnTheFly<T, Ld<T>, Ld<T>> le{F, lq, lq};
-  const int nt = e3[0] * e3[1] * e3[2];
-  for (int it = tid; it < nt; it += nth) {
-    const int ti = it % e3[0], tj = (it / e3[0]) % e3[1], tk = it / (e3[0] * e3[1]);
-    T w[NW];
-    pred_point(F, lo3[0] + ti, lo3[1] + tj, lo3[2] + tk, lq, lq, le, dt, dxp, c, w);
-    const int gi = active(P, 0) ? o3[0] + ti : 0;
-    const int gj = active(P, 1) ? o3[1] + tj : 0;
-    const int gk = active(P, 2) ? o3[2] + tk : 0;
-    store_w(W + P.wbase, (uint32_t)wcell_of(P, g, gi, gj, gk), (uint32_t)P.Nwc, w);
+  for (int it = tid; it < PX * PY * PZ; it += nth) {
+    const int ti = it % PX, tj = (it / PX) % PY, tk = it / (PX * PY);
+    if (ti >= e3[0] || tj >= e3[1] || tk >= e3[2]) continue;
+    const int gi = PX > 1 ? o3[0] + ti : 0;
+    const int gj = PY > 1 ? o3[1] + tj : 0;
+    const int gk = PZ > 1 ? o3[2] + tk : 0;
+    pred_point(F, lo3[0] + ti, lo3[1] + tj, lo3[2] + tk, lq, lq, le, dt, dxp, c,
+               w_store(W + P.wbase, (uint32_t)wcell_of(P, g, gi, gj, gk), (uint32_t)P.Nwc));
   }
   return bad;
 }
@@ -836,7 +854,9 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
   T* ez = SPLIT ? lds : fz + 5 * SH::NFZ;
   T* exx = ez + SH::NEZ;
   T* ey = exx + SH::NEX;
-  const int ax = active(P, 0), ay = active(P, 1), az = active(P, 2);
+  // the tile shape follows the bunch's activity pattern: direction d is active exactly when
+  // the tile extent along d exceeds 1
+  constexpr int ax = TX > 1, ay = TY > 1, az = TZ > 1;
   const int tx = ax ? (P.n[0] - tl.x0 < TX ? P.n[0] - tl.x0 : TX) : 1;
   const int ty = ay ? (P.n[1] - tl.y0 < TY ? P.n[1] - tl.y0 : TY) : 1;
   const int tz = az ? (P.n[2] - tl.z0 < TZ ? P.n[2] - tl.z0 : TZ) : 1;
