@@ -774,10 +774,19 @@ __host__ __device__ __forceinline__ int predict_tile(X& ex, T* L, const PatchDev
   F.ubase = 3 * Nl;
   const int tid = ex.tid(), nth = ex.nthr();
   int bad = 0;
+  // A full tile splits its item index by constants; a ragged tile numbers only its actual
+  // items, so no wavefront runs with most lanes masked.
+  const bool full = e3[0] == PT[0] && e3[1] == PT[1] && e3[2] == PT[2];
   // 1. primitives and face fields of the local box (local index 0 = one cell below the tile)
-  for (int it = tid; it < Nl; it += nth) {
-    const int li = it % LB[0], lj = (it / LB[0]) % LB[1], lk = it / (LB[0] * LB[1]);
-    if (li >= l3[0] || lj >= l3[1] || lk >= l3[2]) continue;
+  const int nl = full ? (int)Nl : l3[0] * l3[1] * l3[2];
+  for (int it0 = tid; it0 < nl; it0 += nth) {
+    int li, lj, lk;
+    if (full) {
+      li = it0 % LB[0]; lj = (it0 / LB[0]) % LB[1]; lk = it0 / (LB[0] * LB[1]);
+    } else {
+      li = it0 % l3[0]; lj = (it0 / l3[0]) % l3[1]; lk = it0 / (l3[0] * l3[1]);
+    }
+    const int it = li + LB[0] * (lj + LB[1] * lk);
     const int gi = PX > 1 ? o3[0] - 1 + li : 0;
     const int gj = PY > 1 ? o3[1] - 1 + lj : 0;
     const int gk = PZ > 1 ? o3[2] - 1 + lk : 0;
@@ -792,9 +801,14 @@ __host__ __device__ __forceinline__ int predict_tile(X& ex, T* L, const PatchDev
   constexpr int lo3[3] = {PX > 1, PY > 1, PZ > 1};
   const Ld<T> lq{L};
   const EnOnTheFly<T, Ld<T>, Ld<T>> le{F, lq, lq};
-  for (int it = tid; it < PX * PY * PZ; it += nth) {
-    const int ti = it % PX, tj = (it / PX) % PY, tk = it / (PX * PY);
-    if (ti >= e3[0] || tj >= e3[1] || tk >= e3[2]) continue;
+  const int nt = full ? PX * PY * PZ : e3[0] * e3[1] * e3[2];
+  for (int it = tid; it < nt; it += nth) {
+    int ti, tj, tk;
+    if (full) {
+      ti = it % PX; tj = (it / PX) % PY; tk = it / (PX * PY);
+    } else {
+      ti = it % e3[0]; tj = (it / e3[0]) % e3[1]; tk = it / (e3[0] * e3[1]);
+    }
     const int gi = PX > 1 ? o3[0] + ti : 0;
     const int gj = PY > 1 ? o3[1] + tj : 0;
     const int gk = PZ > 1 ? o3[2] + tk : 0;
