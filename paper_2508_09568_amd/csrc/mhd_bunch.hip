@@ -106,20 +106,20 @@ __global__ __launch_bounds__(BLK) void k_pred(const PatchDev* __restrict__ pt,
   }
 }
 
-// Where the two-phase tile lets 16 waves (4 per SIMD) share a compute unit's 160 KB of LDS,
-// the waves-per-SIMD hint asks the register allocation to match (<= 128 VGPRs).
+// Waves per SIMD that the shared memory of a solver work-group allows (160 KB per compute
+// unit), capped at 3 in FP64 and 4 in FP32; the hint makes the register allocation fit them
+// (paired loads hold four registers each in FP64).
 template <typename T, int TX, int TY, int TZ, int FORM>
 struct SolveWaves {
   static constexpr int WG = TileShape<TX, TY, TZ>::THREADS / 64;  // waves per work-group
-  static constexpr int value =
-      (FORM != 0 && WG >= 4 && 16 % WG == 0 &&
-       (16 / WG) * TileShape<TX, TY, TZ>::template Lds<FORM>::value * (int)sizeof(T) <= 160 * 1024)
-          ? 4
-          : 1;
+  static constexpr int LDSB = TileShape<TX, TY, TZ>::template Lds<FORM>::value * (int)sizeof(T);
+  static constexpr int BY_LDS = (LDSB > 0 ? (160 * 1024) / LDSB : 8) * WG / 4;
+  static constexpr int CAP = sizeof(T) == 8 ? 3 : 4;
+  static constexpr int value = BY_LDS < 1 ? 1 : (BY_LDS < CAP ? BY_LDS : CAP);
 };
 template <typename T, int TX, int TY, int TZ, int FORM>
-__global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS),
-                             (SolveWaves<T, TX, TY, TZ, FORM>::value)) void k_solve(
+__global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS))
+__attribute__((amdgpu_waves_per_eu(SolveWaves<T, TX, TY, TZ, FORM>::value))) void k_solve(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, const T* __restrict__ Uin,
     T* __restrict__ Uout, const T* __restrict__ S, const double* __restrict__ dt,
     const double* __restrict__ dx, Consts<T> c, int g, int ntile, int remap) {
@@ -154,9 +154,11 @@ __global__ __launch_bounds__((PredShape<PX, PY, PZ>::THREADS),
   if (bad) atomicOr(status, 1);
 }
 
-// half-step edge EMFs, each edge once, by the solver tiles that own them (solver form 2)
+// half-step edge EMFs, each edge once, by the solver tiles that own them (solver form 2); no
+// shared memory: registers alone set the occupancy, three waves per SIMD (<= 168 VGPRs)
 template <typename T, int TX, int TY, int TZ>
-__global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS)) void k_edges(
+__global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS)) __attribute__((amdgpu_waves_per_eu(3)))
+void k_edges(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, T* __restrict__ S,
     const double* __restrict__ dx, Consts<T> c, int g, int ntile, int remap) {
   DevX ex;

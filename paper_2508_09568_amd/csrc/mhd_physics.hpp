@@ -366,31 +366,46 @@ __host__ __device__ __forceinline__ void hlld_flux(const T s[2][7], T bn, const 
 // transport and 2D-extension", Fig. 3: SW/SE/NW/NE).  Each corner C = (rho, u_a, u_b, p,
 // B_e, B_a, B_b) for the edge direction e and its cyclic transverse pair (a, b); W/E are
 // the low/high a sides, S/N the low/high b sides.  Two one-dimensional HLL fluxes of the
-// transverse field, composed, with outer speeds bounded over the four corners.
+// transverse field, composed, with outer speeds bounded over the four corners.  The corners
+// are taken one at a time (0 SW, 1 SE, 2 NW, 3 NE), so a caller need not hold all four
+// states; the speed bounds are maxima, exact in any order.
 template <typename T>
-__host__ __device__ __forceinline__ T uct_emf(const T C[4][7], const Consts<T>& c) {
+struct UctAcc {
   T emf[4];
-  T apa = T(0), ama = T(0), apb = T(0), amb = T(0);
-  for (int k = 0; k < 4; ++k) {
-    const T r = C[k][0], ua = C[k][1], ubb = C[k][2], p = C[k][3];
-    const T be = C[k][4], ba = C[k][5], bb = C[k][6];
+  T apa, ama, apb, amb;
+  T ba0, bb0, bb1, ba2;  // B_a, B_b of SW; B_b of SE; B_a of NW
+  __host__ __device__ __forceinline__ UctAcc() : apa(T(0)), ama(T(0)), apb(T(0)), amb(T(0)) {}
+  __host__ __device__ __forceinline__ void add(int k, const T C[7], const Consts<T>& c) {
+    const T r = C[0], ua = C[1], ubb = C[2], p = C[3];
+    const T be = C[4], ba = C[5], bb = C[6];
     emf[k] = ua * bb - ubb * ba;
-    const T ba2 = ba * ba, bb2 = bb * bb, be2 = be * be;
-    const WaveBase<T> wb = wave_base(r, p, ba2 + bb2 + be2, c.gamma);
+    const T ba2_ = ba * ba, bb2 = bb * bb, be2 = be * be;
+    const WaveBase<T> wb = wave_base(r, p, ba2_ + bb2 + be2, c.gamma);
     const T cfa = fast_speed_t(wb, bb2 + be2);
-    const T cfb = fast_speed_t(wb, be2 + ba2);
+    const T cfb = fast_speed_t(wb, be2 + ba2_);
     apa = m_max(apa, ua + cfa);
     ama = m_max(ama, cfa - ua);
     apb = m_max(apb, ubb + cfb);
     amb = m_max(amb, cfb - ubb);
+    if (k == 0) { ba0 = ba; bb0 = bb; }
+    if (k == 1) bb1 = bb;
+    if (k == 2) ba2 = ba;
   }
-  const T da = m_max(apa + ama, c.tiny);
-  const T db = m_max(apb + amb, c.tiny);
-  // corners: 0 SW, 1 SE, 2 NW, 3 NE
-  const T ida = m_rcp(da), idb = m_rcp(db);
-  const T avg = (apa * apb * emf[0] + apa * amb * emf[2] + ama * apb * emf[1] + ama * amb * emf[3]) *
-                (ida * idb);
-  return avg - apa * ama * ida * (C[1][6] - C[0][6]) + apb * amb * idb * (C[2][5] - C[0][5]);
+  __host__ __device__ __forceinline__ T finish(const Consts<T>& c) const {
+    const T da = m_max(apa + ama, c.tiny);
+    const T db = m_max(apb + amb, c.tiny);
+    const T ida = m_rcp(da), idb = m_rcp(db);
+    const T avg = (apa * apb * emf[0] + apa * amb * emf[2] + ama * apb * emf[1] + ama * amb * emf[3]) *
+                  (ida * idb);
+    return avg - apa * ama * ida * (bb1 - bb0) + apb * amb * idb * (ba2 - ba0);
+  }
+};
+template <typename T>
+__host__ __device__ __forceinline__ T uct_emf(const T C[4][7], const Consts<T>& c) {
+  UctAcc<T> u;
+  #pragma unroll
+  for (int k = 0; k < 4; ++k) u.add(k, C[k], c);
+  return u.finish(c);
 }
 
 }  // namespace mhd

@@ -145,6 +145,21 @@ struct LdRel {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) +
                                        (uint32_t)(i * (uint32_t)sizeof(T)));
   }
+  // elements i and i + 1 (x neighbours in a predictor block) by one memory instruction: the
+  // vector units fetch 16 bytes per lane at the cost of 8 (the address only needs the
+  // element's own alignment)
+  __host__ __device__ __forceinline__ void pair(uint32_t i, T& a, T& b) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef T v2 __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+    const v2 v = *reinterpret_cast<const v2*>(reinterpret_cast<const char*>(p) +
+                                              (uint32_t)(i * (uint32_t)sizeof(T)));
+    a = v.x;
+    b = v.y;
+#else
+    a = (*this)(i);
+    b = (*this)(i + 1);
+#endif
+  }
 };
 
 template <typename T>
@@ -327,6 +342,27 @@ __host__ __device__ __forceinline__ void face_point(const PatchDev& P, int g, in
   hlld_flux(s, bn, c, F);
 }
 
+// predicted corner state at corner (sa, sb) of a cell for an edge along e, from the cell's
+// values v and slopes along a and b (sla, slb) of the components (rho, u_a, u_b, p, B_e), and
+// the face fields BA, BB with their transverse slopes tA, tB on the faces the corner touches:
+// (rho, u_a, u_b, p, B_e, B_a, B_b)
+template <typename S>
+__host__ __device__ __forceinline__ void corner_from(const S v[5], const S sla[5], const S slb[5],
+                                                     S BA, S tA, S BB, S tB, int sa, int sb,
+                                                     const Consts<S>& c, S C[7]) {
+  for (int t = 0; t < 5; ++t) {
+    const S ha = S(0.5) * sla[t];
+    const S hb = S(0.5) * slb[t];
+    C[t] = v[t] + ((sa > 0 ? ha : -ha) + (sb > 0 ? hb : -hb));
+  }
+  const S ta = S(0.5) * tA;
+  const S tb = S(0.5) * tB;
+  C[5] = BA + (sb > 0 ? ta : -ta);
+  C[6] = BB + (sa > 0 ? tb : -tb);
+  if (C[0] < c.rho_floor) C[0] = c.rho_floor;
+  if (C[3] < c.p_floor) C[3] = c.p_floor;
+}
+
 // predicted corner state of predictor cell wc (index in the patch's predictor box) at corner
 // (sa, sb) for an edge along e: (rho, u_a, u_b, p, B_e, B_a, B_b)
 template <typename S, class AW>
@@ -336,20 +372,17 @@ __host__ __device__ __forceinline__ void corner_state(const PatchDev& P, const A
   const uint32_t Nw = (uint32_t)P.Nwc;
   const int a = (e + 1) % 3, b = (e + 2) % 3;
   const int comp[5] = {0, 1 + a, 1 + b, 4, 5 + e};
+  S v[5], sla[5], slb[5];
   for (int t = 0; t < 5; ++t) {
     const int m = comp[t];
-    const S ha = S(0.5) * w(wc + slope_slot(a, m) * Nw);
-    const S hb = S(0.5) * w(wc + slope_slot(b, m) * Nw);
-    C[t] = w(wc + m * Nw) + ((sa > 0 ? ha : -ha) + (sb > 0 ? hb : -hb));
+    v[t] = w(wc + m * Nw);
+    sla[t] = w(wc + slope_slot(a, m) * Nw);
+    slb[t] = w(wc + slope_slot(b, m) * Nw);
   }
   const uint32_t fa = wc + (sa > 0 ? (uint32_t)P.woff[a] : 0u);
   const uint32_t fb = wc + (sb > 0 ? (uint32_t)P.woff[b] : 0u);
-  const S ta = S(0.5) * w(fa + dbf_slot(a, b) * Nw);
-  const S tb = S(0.5) * w(fb + dbf_slot(b, a) * Nw);
-  C[5] = w(fa + (W_BH + a) * Nw) + (sb > 0 ? ta : -ta);
-  C[6] = w(fb + (W_BH + b) * Nw) + (sa > 0 ? tb : -tb);
-  if (C[0] < c.rho_floor) C[0] = c.rho_floor;
-  if (C[3] < c.p_floor) C[3] = c.p_floor;
+  corner_from(v, sla, slb, w(fa + (W_BH + a) * Nw), w(fa + dbf_slot(a, b) * Nw),
+              w(fb + (W_BH + b) * Nw), w(fb + dbf_slot(b, a) * Nw), sa, sb, c, C);
 }
 
 // -------------------------------------------------------- stage 4b: edge EMF
@@ -366,6 +399,198 @@ __host__ __device__ __forceinline__ S edge_point(const PatchDev& P, int g, int e
   corner_state(P, w, wc - oa, e, +1, -1, c, C[2]);       // NW
   corner_state(P, w, wc, e, -1, -1, c, C[3]);            // NE
   return uct_emf(C, c);
+}
+
+// Scheduling fence (device code): instructions are not moved across it, which bounds how many
+// paired loads the compiler issues ahead of the arithmetic that consumes them (each holds four
+// registers in FP64) and so the register count of the kernels that use them.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MHD_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define MHD_SCHED_FENCE() ((void)0)
+#endif
+
+// ----------------------------------- paired forms (x neighbours by one memory access)
+// The same items as face_point and edge_point, with the same arithmetic, for a patch whose x
+// direction is active: the values of x-neighbour cells come in pairs (LdRel::pair).
+//  - face_x_point: one x face (its two sides are x neighbours);
+//  - face_pair_point<D>: the D faces (D = 1, 2) of cells i and i + 1;
+//  - edge_px_point<E>: one edge along E = 1 or 2 (two of its corners are x neighbours of the
+//    other two);
+//  - edge_pair_x_point: the x edges of cells i and i + 1.
+// Slot values of the 5 corner components and their slopes along a and b of cell wc and of
+// wc + 1 (for one edge direction E).
+template <int E, typename S, class AW>
+__host__ __device__ __forceinline__ void corner_vals_pair(const AW& w, uint32_t wc, uint32_t Nw,
+                                                          S v[2][5], S sla[2][5], S slb[2][5]) {
+  constexpr int a = (E + 1) % 3, b = (E + 2) % 3;
+  constexpr int comp[5] = {0, 1 + a, 1 + b, 4, 5 + E};
+  #pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    const int m = comp[t];
+    w.pair(wc + m * Nw, v[0][t], v[1][t]);
+    w.pair(wc + slope_slot(a, m) * Nw, sla[0][t], sla[1][t]);
+    w.pair(wc + slope_slot(b, m) * Nw, slb[0][t], slb[1][t]);
+  }
+}
+
+template <typename S, class AW>
+__host__ __device__ __forceinline__ void face_x_point(const PatchDev& P, int g, int i, int j, int k,
+                                                      const AW& w, const Consts<S>& c, S F[5]) {
+  const uint32_t Nw = (uint32_t)P.Nwc;
+  const uint32_t wl = (uint32_t)wcell_of(P, g, i, j, k) - 1u;
+  constexpr int comp[7] = {0, 1, 2, 3, 4, 6, 7};
+  S s[2][7];
+  #pragma unroll
+  for (int t = 0; t < 7; ++t) {
+    const int m = comp[t];
+    S vl, vr, ql, qr;
+    w.pair(wl + m * Nw, vl, vr);
+    w.pair(wl + slope_slot(0, m) * Nw, ql, qr);
+    s[0][t] = vl + S(0.5) * ql;
+    s[1][t] = vr - S(0.5) * qr;
+  }
+  #pragma unroll
+  for (int k2 = 0; k2 < 2; ++k2) {
+    if (s[k2][0] < c.rho_floor) s[k2][0] = c.rho_floor;
+    if (s[k2][4] < c.p_floor) s[k2][4] = c.p_floor;
+  }
+  hlld_flux(s, w(wl + 1u + W_BH * Nw), c, F);
+}
+
+template <int D, typename S, class AW>
+__host__ __device__ __forceinline__ void face_pair_point(const PatchDev& P, int g, int i, int j, int k,
+                                                         const AW& w, const Consts<S>& c,
+                                                         S F[2][5]) {
+  const uint32_t Nw = (uint32_t)P.Nwc;
+  const uint32_t wr = (uint32_t)wcell_of(P, g, i, j, k);
+  const uint32_t wl = wr - (uint32_t)P.woff[D];
+  constexpr int a = (D + 1) % 3, b = (D + 2) % 3;
+  constexpr int comp[7] = {0, 1 + D, 1 + a, 1 + b, 4, 5 + a, 5 + b};
+  S s[2][2][7];  // [cell of the pair][side][component]
+  #pragma unroll
+  for (int t = 0; t < 7; ++t) {
+    const int m = comp[t];
+    const int sl = slope_slot(D, m);
+    S vl[2], ql[2], vr[2], qr[2];
+    w.pair(wl + m * Nw, vl[0], vl[1]);
+    w.pair(wl + sl * Nw, ql[0], ql[1]);
+    w.pair(wr + m * Nw, vr[0], vr[1]);
+    w.pair(wr + sl * Nw, qr[0], qr[1]);
+    #pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      s[h][0][t] = vl[h] + S(0.5) * ql[h];
+      s[h][1][t] = vr[h] - S(0.5) * qr[h];
+    }
+  }
+  S bn[2];
+  w.pair(wr + (W_BH + D) * Nw, bn[0], bn[1]);
+  #pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    #pragma unroll
+    for (int k2 = 0; k2 < 2; ++k2) {
+      if (s[h][k2][0] < c.rho_floor) s[h][k2][0] = c.rho_floor;
+      if (s[h][k2][4] < c.p_floor) s[h][k2][4] = c.p_floor;
+    }
+    hlld_flux(s[h], bn[h], c, F[h]);
+    MHD_SCHED_FENCE();
+  }
+}
+
+template <int E, typename S, class AW>
+__host__ __device__ __forceinline__ S edge_px_point(const PatchDev& P, int g, int i, int j, int k,
+                                                    const AW& w, const Consts<S>& c) {
+  static_assert(E == 1 || E == 2, "edges along y or z");
+  constexpr int a = (E + 1) % 3, b = (E + 2) % 3;
+  const uint32_t Nw = (uint32_t)P.Nwc;
+  const uint32_t wc = (uint32_t)wcell_of(P, g, i, j, k);
+  // the transverse direction that is not x: corners one cell apart along it
+  constexpr int t = E == 2 ? b : a;  // E = z: (a, b) = (x, y); E = y: (a, b) = (z, x)
+  const uint32_t ot = (uint32_t)P.woff[t];
+  UctAcc<S> u;
+  #pragma unroll
+  for (int row = 0; row < 2; ++row) {
+    // cells (x - 1, row) and (x, row) along t: row 0 at t - 1, row 1 at t
+    const uint32_t c0 = wc - 1u - (row == 0 ? ot : 0u);
+    S v[2][5], sla[2][5], slb[2][5];
+    corner_vals_pair<E>(w, c0, Nw, v, sla, slb);
+    // corner signs (sa, sb) and corner index of the x - 1 and x cells of this row
+    int sa[2], sb[2], kk[2];
+    if (E == 2) {  // a = x, b = y: row 0 = (SW, SE), row 1 = (NW, NE)
+      sa[0] = +1; sa[1] = -1;
+      sb[0] = sb[1] = row == 0 ? +1 : -1;
+      kk[0] = row == 0 ? 0 : 2;
+      kk[1] = row == 0 ? 1 : 3;
+    } else {       // a = z, b = x: row 0 (z - 1) = (SW, NW), row 1 (z) = (SE, NE)
+      sa[0] = sa[1] = row == 0 ? +1 : -1;
+      sb[0] = +1; sb[1] = -1;
+      kk[0] = row == 0 ? 0 : 1;
+      kk[1] = row == 0 ? 2 : 3;
+    }
+    S BA[2], tA[2], BB[2], tB[2];
+    #pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t cell = c0 + (uint32_t)h;
+      const uint32_t fa = cell + (sa[h] > 0 ? (uint32_t)P.woff[a] : 0u);
+      const uint32_t fb = cell + (sb[h] > 0 ? (uint32_t)P.woff[b] : 0u);
+      if (h == 0) {
+        // the face values of both corners of the row, paired where they are x neighbours
+        if (E == 2) {  // a = x: both corners read B_x on the face at x (cell c0 + 1)
+          BA[0] = BA[1] = w(c0 + 1u + (W_BH + a) * Nw);
+          tA[0] = tA[1] = w(c0 + 1u + dbf_slot(a, b) * Nw);
+          w.pair(fb + (W_BH + b) * Nw, BB[0], BB[1]);
+          w.pair(fb + dbf_slot(b, a) * Nw, tB[0], tB[1]);
+        } else {       // b = x: both corners read B_x on the face at x (cell c0 + 1)
+          w.pair(fa + (W_BH + a) * Nw, BA[0], BA[1]);
+          w.pair(fa + dbf_slot(a, b) * Nw, tA[0], tA[1]);
+          BB[0] = BB[1] = w(c0 + 1u + (W_BH + b) * Nw);
+          tB[0] = tB[1] = w(c0 + 1u + dbf_slot(b, a) * Nw);
+        }
+      }
+    }
+    S C[2][7];
+    #pragma unroll
+    for (int h = 0; h < 2; ++h)
+      corner_from(v[h], sla[h], slb[h], BA[h], tA[h], BB[h], tB[h], sa[h], sb[h], c, C[h]);
+    u.add(kk[0], C[0], c);
+    u.add(kk[1], C[1], c);
+    MHD_SCHED_FENCE();
+  }
+  return u.finish(c);
+}
+
+template <typename S, class AW>
+__host__ __device__ __forceinline__ void edge_pair_x_point(const PatchDev& P, int g, int i, int j,
+                                                           int k, const AW& w, const Consts<S>& c,
+                                                           S E2[2]) {
+  constexpr int a = 1, b = 2;  // edges along x: (a, b) = (y, z)
+  const uint32_t Nw = (uint32_t)P.Nwc;
+  const uint32_t wc = (uint32_t)wcell_of(P, g, i, j, k);
+  const uint32_t oa = (uint32_t)P.woff[a], ob = (uint32_t)P.woff[b];
+  const uint32_t cell[4] = {wc - oa - ob, wc - ob, wc - oa, wc};  // SW, SE, NW, NE
+  const int sa[4] = {+1, -1, +1, -1}, sb[4] = {+1, +1, -1, -1};
+  UctAcc<S> u[2];
+  #pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    S v[2][5], sla[2][5], slb[2][5];
+    corner_vals_pair<0>(w, cell[q], Nw, v, sla, slb);
+    const uint32_t fa = cell[q] + (sa[q] > 0 ? oa : 0u);
+    const uint32_t fb = cell[q] + (sb[q] > 0 ? ob : 0u);
+    S BA[2], tA[2], BB[2], tB[2];
+    w.pair(fa + (W_BH + a) * Nw, BA[0], BA[1]);
+    w.pair(fa + dbf_slot(a, b) * Nw, tA[0], tA[1]);
+    w.pair(fb + (W_BH + b) * Nw, BB[0], BB[1]);
+    w.pair(fb + dbf_slot(b, a) * Nw, tB[0], tB[1]);
+    #pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      S C[7];
+      corner_from(v[h], sla[h], slb[h], BA[h], tA[h], BB[h], tB[h], sa[q], sb[q], c, C);
+      u[h].add(q, C, c);
+    }
+    MHD_SCHED_FENCE();
+  }
+  E2[0] = u[0].finish(c);
+  E2[1] = u[1].finish(c);
 }
 
 // ------------------------------------------------ forward writers of stages 1-3
@@ -887,10 +1112,17 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
   // beyond the tile's actual extent (ragged tiles, collapsed directions) are skipped.
   // SPLIT: faces first (then the hydro update), edges after (then the field update), so
   // flux and EMF arrays share the shared memory.
+  // With x active, every item reads the values of x-neighbour cells in pairs (one memory
+  // instruction for two values), and the y faces, z faces and x edges, whose own cells are not
+  // x neighbours, are taken two per lane (cells x and x + 1) to pair them.
   constexpr int WAVE = 64;
+  constexpr bool PR = TX > 1;
+  constexpr bool TWO = false;  // y/z faces and x edges two per lane
+  static_assert(!PR || TX % 2 == 0, "paired items need an even tile extent along x");
+  constexpr int XP = PR && TWO ? TX / 2 : TX, XM = PR && TWO ? 2 : 1;  // lanes per row of the paired segments
   constexpr int X1 = TX > 1 ? TX + 1 : 1, Y1 = TY > 1 ? TY + 1 : 1, Z1 = TZ > 1 ? TZ + 1 : 1;
-  constexpr int NS[6] = {X1 * TY * TZ, TX * Y1 * TZ, TX * TY * Z1,
-                         TX * Y1 * Z1, X1 * TY * Z1, X1 * Y1 * TZ};
+  constexpr int NS[6] = {X1 * TY * TZ, XP * Y1 * TZ, XP * TY * Z1,
+                         XP * Y1 * Z1, X1 * TY * Z1, X1 * Y1 * TZ};
   constexpr int B1 = (NS[0] + WAVE - 1) / WAVE * WAVE, B2 = B1 + (NS[1] + WAVE - 1) / WAVE * WAVE,
                 B3 = B2 + (NS[2] + WAVE - 1) / WAVE * WAVE, B4 = B3 + (NS[3] + WAVE - 1) / WAVE * WAVE,
                 B5 = B4 + (NS[4] + WAVE - 1) / WAVE * WAVE, B6 = B5 + (NS[5] + WAVE - 1) / WAVE * WAVE;
@@ -902,6 +1134,7 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
   const int64_t Nc = P.Nc;
   const T* u = Uin + P.ubase;
   T* uo = Uout + P.ubase;
+  const LdRel<T> wa{Win + P.wbase};
 
   for (int phase = 0; phase < (SPLIT ? 2 : 1); ++phase) {
     if (EDGES) {
@@ -910,7 +1143,7 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         const int k = wave_uniform(it < B4 ? 3 : it < B5 ? 4 : 5);
         int lx, ly, lz;
         switch (k) {
-          case 3: { const int r = it - B3; lx = r % TX; ly = (r / TX) % Y1; lz = r / (TX * Y1); break; }
+          case 3: { const int r = it - B3; lx = XM * (r % XP); ly = (r / XP) % Y1; lz = r / (XP * Y1); break; }
           case 4: { const int r = it - B4; lx = r % X1; ly = (r / X1) % TY; lz = r / (X1 * TY); break; }
           default: { const int r = it - B5; lx = r % X1; ly = (r / X1) % Y1; lz = r / (X1 * Y1); break; }
         }
@@ -920,7 +1153,23 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         const int e2 = tz + (e != 2 && az && tl.z0 + tz == P.n[2]);
         if (lx >= e0 || ly >= e1 || lz >= e2) continue;
         const int64_t cg = cell_of(P, i0 + lx, j0 + ly, k0 + lz);
-        const_cast<T*>(eg)[e * Nc + cg] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
+        T* eo = const_cast<T*>(eg) + e * Nc + cg;
+        if (PR) {
+          if (e == 0 && TWO) {
+            T E2[2];
+            edge_pair_x_point(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c, E2);
+            eo[0] = E2[0];
+            if (lx + 1 < e0) eo[1] = E2[1];
+          } else if (e == 0) {
+            eo[0] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
+          } else if (e == 1) {
+            eo[0] = edge_px_point<1>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
+          } else {
+            eo[0] = edge_px_point<2>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
+          }
+        } else {
+          eo[0] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
+        }
       }
       return;
     }
@@ -931,9 +1180,9 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
       int lx, ly, lz, e0, e1, e2;
       switch (k) {
         case 0: { const int r = it;      lx = r % X1; ly = (r / X1) % TY; lz = r / (X1 * TY); break; }
-        case 1: { const int r = it - B1; lx = r % TX; ly = (r / TX) % Y1; lz = r / (TX * Y1); break; }
-        case 2: { const int r = it - B2; lx = r % TX; ly = (r / TX) % TY; lz = r / (TX * TY); break; }
-        case 3: { const int r = it - B3; lx = r % TX; ly = (r / TX) % Y1; lz = r / (TX * Y1); break; }
+        case 1: { const int r = it - B1; lx = XM * (r % XP); ly = (r / XP) % Y1; lz = r / (XP * Y1); break; }
+        case 2: { const int r = it - B2; lx = XM * (r % XP); ly = (r / XP) % TY; lz = r / (XP * TY); break; }
+        case 3: { const int r = it - B3; lx = XM * (r % XP); ly = (r / XP) % Y1; lz = r / (XP * Y1); break; }
         case 4: { const int r = it - B4; lx = r % X1; ly = (r / X1) % TY; lz = r / (X1 * TY); break; }
         default: { const int r = it - B5; lx = r % X1; ly = (r / X1) % Y1; lz = r / (X1 * Y1); break; }
       }
@@ -949,14 +1198,31 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         T* fd = d == 0 ? fx : (d == 1 ? fy : fz);
         const int NF = d == 0 ? SH::NFX : (d == 1 ? SH::NFY : SH::NFZ);
         const int a = (d + 1) % 3, b = (d + 2) % 3;
-        T F[5];
-        face_flux_item(P, g, d, i0 + lx, j0 + ly, k0 + lz, Win, c, F);
-        const int li = lx + LX * (ly + LY * lz);
-        fd[0 * NF + li] = F[0];
-        fd[(1 + d) * NF + li] = F[1];
-        fd[(1 + a) * NF + li] = F[2];
-        fd[(1 + b) * NF + li] = F[3];
-        fd[4 * NF + li] = F[4];
+        T F[2][5];
+        int nitem = 1;
+        if (PR) {
+          if (d == 0) {
+            face_x_point(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c, F[0]);
+          } else if (!TWO) {
+            face_flux_item(P, g, d, i0 + lx, j0 + ly, k0 + lz, Win, c, F[0]);
+          } else {
+            if (d == 1)
+              face_pair_point<1>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c, F);
+            else
+              face_pair_point<2>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c, F);
+            nitem = lx + 1 < e0 ? 2 : 1;
+          }
+        } else {
+          face_flux_item(P, g, d, i0 + lx, j0 + ly, k0 + lz, Win, c, F[0]);
+        }
+        for (int h = 0; h < nitem; ++h) {
+          const int li = lx + h + LX * (ly + LY * lz);
+          fd[0 * NF + li] = F[h][0];
+          fd[(1 + d) * NF + li] = F[h][1];
+          fd[(1 + a) * NF + li] = F[h][2];
+          fd[(1 + b) * NF + li] = F[h][3];
+          fd[4 * NF + li] = F[h][4];
+        }
       } else if (!EXT) {
         // edge along e: extents t + 1 along the two transverse directions when active
         const int e = k - 3;
@@ -966,7 +1232,23 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         if (lx >= e0 || ly >= e1 || lz >= e2) continue;
         const int LX = TX + (e != 0), LY = TY + (e != 1);
         T* ed = e == 0 ? exx : (e == 1 ? ey : ez);
-        ed[lx + LX * (ly + LY * lz)] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
+        const int li = lx + LX * (ly + LY * lz);
+        if (PR) {
+          if (e == 0 && TWO) {
+            T E2[2];
+            edge_pair_x_point(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c, E2);
+            ed[li] = E2[0];
+            if (lx + 1 < e0) ed[li + 1] = E2[1];
+          } else if (e == 0) {
+            ed[li] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
+          } else if (e == 1) {
+            ed[li] = edge_px_point<1>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
+          } else {
+            ed[li] = edge_px_point<2>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
+          }
+        } else {
+          ed[li] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
+        }
       }
     }
     ex.sync();
