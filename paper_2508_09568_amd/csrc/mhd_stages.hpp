@@ -414,10 +414,10 @@ __host__ __device__ __forceinline__ S edge_point(const PatchDev& P, int g, int e
 // The same items as face_point and edge_point, with the same arithmetic, for a patch whose x
 // direction is active: the values of x-neighbour cells come in pairs (LdRel::pair).
 //  - face_x_point: one x face (its two sides are x neighbours);
-//  - face_pair_point<D>: the D faces (D = 1, 2) of cells i and i + 1;
 //  - edge_px_point<E>: one edge along E = 1 or 2 (two of its corners are x neighbours of the
-//    other two);
-//  - edge_pair_x_point: the x edges of cells i and i + 1.
+//    other two).
+// (Taking the y/z faces and x edges two per lane to pair them as well measured slower in FP64:
+// the extra live state spills at the occupancy the shared memory allows.)
 // Slot values of the 5 corner components and their slopes along a and b of cell wc and of
 // wc + 1 (for one edge direction E).
 template <int E, typename S, class AW>
@@ -456,45 +456,6 @@ __host__ __device__ __forceinline__ void face_x_point(const PatchDev& P, int g, 
     if (s[k2][4] < c.p_floor) s[k2][4] = c.p_floor;
   }
   hlld_flux(s, w(wl + 1u + W_BH * Nw), c, F);
-}
-
-template <int D, typename S, class AW>
-__host__ __device__ __forceinline__ void face_pair_point(const PatchDev& P, int g, int i, int j, int k,
-                                                         const AW& w, const Consts<S>& c,
-                                                         S F[2][5]) {
-  const uint32_t Nw = (uint32_t)P.Nwc;
-  const uint32_t wr = (uint32_t)wcell_of(P, g, i, j, k);
-  const uint32_t wl = wr - (uint32_t)P.woff[D];
-  constexpr int a = (D + 1) % 3, b = (D + 2) % 3;
-  constexpr int comp[7] = {0, 1 + D, 1 + a, 1 + b, 4, 5 + a, 5 + b};
-  S s[2][2][7];  // [cell of the pair][side][component]
-  #pragma unroll
-  for (int t = 0; t < 7; ++t) {
-    const int m = comp[t];
-    const int sl = slope_slot(D, m);
-    S vl[2], ql[2], vr[2], qr[2];
-    w.pair(wl + m * Nw, vl[0], vl[1]);
-    w.pair(wl + sl * Nw, ql[0], ql[1]);
-    w.pair(wr + m * Nw, vr[0], vr[1]);
-    w.pair(wr + sl * Nw, qr[0], qr[1]);
-    #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      s[h][0][t] = vl[h] + S(0.5) * ql[h];
-      s[h][1][t] = vr[h] - S(0.5) * qr[h];
-    }
-  }
-  S bn[2];
-  w.pair(wr + (W_BH + D) * Nw, bn[0], bn[1]);
-  #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    #pragma unroll
-    for (int k2 = 0; k2 < 2; ++k2) {
-      if (s[h][k2][0] < c.rho_floor) s[h][k2][0] = c.rho_floor;
-      if (s[h][k2][4] < c.p_floor) s[h][k2][4] = c.p_floor;
-    }
-    hlld_flux(s[h], bn[h], c, F[h]);
-    MHD_SCHED_FENCE();
-  }
 }
 
 template <int E, typename S, class AW>
@@ -557,40 +518,6 @@ __host__ __device__ __forceinline__ S edge_px_point(const PatchDev& P, int g, in
     MHD_SCHED_FENCE();
   }
   return u.finish(c);
-}
-
-template <typename S, class AW>
-__host__ __device__ __forceinline__ void edge_pair_x_point(const PatchDev& P, int g, int i, int j,
-                                                           int k, const AW& w, const Consts<S>& c,
-                                                           S E2[2]) {
-  constexpr int a = 1, b = 2;  // edges along x: (a, b) = (y, z)
-  const uint32_t Nw = (uint32_t)P.Nwc;
-  const uint32_t wc = (uint32_t)wcell_of(P, g, i, j, k);
-  const uint32_t oa = (uint32_t)P.woff[a], ob = (uint32_t)P.woff[b];
-  const uint32_t cell[4] = {wc - oa - ob, wc - ob, wc - oa, wc};  // SW, SE, NW, NE
-  const int sa[4] = {+1, -1, +1, -1}, sb[4] = {+1, +1, -1, -1};
-  UctAcc<S> u[2];
-  #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    S v[2][5], sla[2][5], slb[2][5];
-    corner_vals_pair<0>(w, cell[q], Nw, v, sla, slb);
-    const uint32_t fa = cell[q] + (sa[q] > 0 ? oa : 0u);
-    const uint32_t fb = cell[q] + (sb[q] > 0 ? ob : 0u);
-    S BA[2], tA[2], BB[2], tB[2];
-    w.pair(fa + (W_BH + a) * Nw, BA[0], BA[1]);
-    w.pair(fa + dbf_slot(a, b) * Nw, tA[0], tA[1]);
-    w.pair(fb + (W_BH + b) * Nw, BB[0], BB[1]);
-    w.pair(fb + dbf_slot(b, a) * Nw, tB[0], tB[1]);
-    #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      S C[7];
-      corner_from(v[h], sla[h], slb[h], BA[h], tA[h], BB[h], tB[h], sa[q], sb[q], c, C);
-      u[h].add(q, C, c);
-    }
-    MHD_SCHED_FENCE();
-  }
-  E2[0] = u[0].finish(c);
-  E2[1] = u[1].finish(c);
 }
 
 // ------------------------------------------------ forward writers of stages 1-3
@@ -1112,17 +1039,13 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
   // beyond the tile's actual extent (ragged tiles, collapsed directions) are skipped.
   // SPLIT: faces first (then the hydro update), edges after (then the field update), so
   // flux and EMF arrays share the shared memory.
-  // With x active, every item reads the values of x-neighbour cells in pairs (one memory
-  // instruction for two values), and the y faces, z faces and x edges, whose own cells are not
-  // x neighbours, are taken two per lane (cells x and x + 1) to pair them.
+  // With x active, the x faces and the y and z edges read the values of x-neighbour cells in
+  // pairs (one memory instruction for two values).
   constexpr int WAVE = 64;
   constexpr bool PR = TX > 1;
-  constexpr bool TWO = false;  // y/z faces and x edges two per lane
-  static_assert(!PR || TX % 2 == 0, "paired items need an even tile extent along x");
-  constexpr int XP = PR && TWO ? TX / 2 : TX, XM = PR && TWO ? 2 : 1;  // lanes per row of the paired segments
   constexpr int X1 = TX > 1 ? TX + 1 : 1, Y1 = TY > 1 ? TY + 1 : 1, Z1 = TZ > 1 ? TZ + 1 : 1;
-  constexpr int NS[6] = {X1 * TY * TZ, XP * Y1 * TZ, XP * TY * Z1,
-                         XP * Y1 * Z1, X1 * TY * Z1, X1 * Y1 * TZ};
+  constexpr int NS[6] = {X1 * TY * TZ, TX * Y1 * TZ, TX * TY * Z1,
+                         TX * Y1 * Z1, X1 * TY * Z1, X1 * Y1 * TZ};
   constexpr int B1 = (NS[0] + WAVE - 1) / WAVE * WAVE, B2 = B1 + (NS[1] + WAVE - 1) / WAVE * WAVE,
                 B3 = B2 + (NS[2] + WAVE - 1) / WAVE * WAVE, B4 = B3 + (NS[3] + WAVE - 1) / WAVE * WAVE,
                 B5 = B4 + (NS[4] + WAVE - 1) / WAVE * WAVE, B6 = B5 + (NS[5] + WAVE - 1) / WAVE * WAVE;
@@ -1143,7 +1066,7 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         const int k = wave_uniform(it < B4 ? 3 : it < B5 ? 4 : 5);
         int lx, ly, lz;
         switch (k) {
-          case 3: { const int r = it - B3; lx = XM * (r % XP); ly = (r / XP) % Y1; lz = r / (XP * Y1); break; }
+          case 3: { const int r = it - B3; lx = r % TX; ly = (r / TX) % Y1; lz = r / (TX * Y1); break; }
           case 4: { const int r = it - B4; lx = r % X1; ly = (r / X1) % TY; lz = r / (X1 * TY); break; }
           default: { const int r = it - B5; lx = r % X1; ly = (r / X1) % Y1; lz = r / (X1 * Y1); break; }
         }
@@ -1154,22 +1077,12 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         if (lx >= e0 || ly >= e1 || lz >= e2) continue;
         const int64_t cg = cell_of(P, i0 + lx, j0 + ly, k0 + lz);
         T* eo = const_cast<T*>(eg) + e * Nc + cg;
-        if (PR) {
-          if (e == 0 && TWO) {
-            T E2[2];
-            edge_pair_x_point(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c, E2);
-            eo[0] = E2[0];
-            if (lx + 1 < e0) eo[1] = E2[1];
-          } else if (e == 0) {
-            eo[0] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
-          } else if (e == 1) {
-            eo[0] = edge_px_point<1>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
-          } else {
-            eo[0] = edge_px_point<2>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
-          }
-        } else {
+        if (PR && e == 1)
+          eo[0] = edge_px_point<1>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
+        else if (PR && e == 2)
+          eo[0] = edge_px_point<2>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
+        else
           eo[0] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
-        }
       }
       return;
     }
@@ -1180,9 +1093,9 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
       int lx, ly, lz, e0, e1, e2;
       switch (k) {
         case 0: { const int r = it;      lx = r % X1; ly = (r / X1) % TY; lz = r / (X1 * TY); break; }
-        case 1: { const int r = it - B1; lx = XM * (r % XP); ly = (r / XP) % Y1; lz = r / (XP * Y1); break; }
-        case 2: { const int r = it - B2; lx = XM * (r % XP); ly = (r / XP) % TY; lz = r / (XP * TY); break; }
-        case 3: { const int r = it - B3; lx = XM * (r % XP); ly = (r / XP) % Y1; lz = r / (XP * Y1); break; }
+        case 1: { const int r = it - B1; lx = r % TX; ly = (r / TX) % Y1; lz = r / (TX * Y1); break; }
+        case 2: { const int r = it - B2; lx = r % TX; ly = (r / TX) % TY; lz = r / (TX * TY); break; }
+        case 3: { const int r = it - B3; lx = r % TX; ly = (r / TX) % Y1; lz = r / (TX * Y1); break; }
         case 4: { const int r = it - B4; lx = r % X1; ly = (r / X1) % TY; lz = r / (X1 * TY); break; }
         default: { const int r = it - B5; lx = r % X1; ly = (r / X1) % Y1; lz = r / (X1 * Y1); break; }
       }
@@ -1198,31 +1111,17 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         T* fd = d == 0 ? fx : (d == 1 ? fy : fz);
         const int NF = d == 0 ? SH::NFX : (d == 1 ? SH::NFY : SH::NFZ);
         const int a = (d + 1) % 3, b = (d + 2) % 3;
-        T F[2][5];
-        int nitem = 1;
-        if (PR) {
-          if (d == 0) {
-            face_x_point(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c, F[0]);
-          } else if (!TWO) {
-            face_flux_item(P, g, d, i0 + lx, j0 + ly, k0 + lz, Win, c, F[0]);
-          } else {
-            if (d == 1)
-              face_pair_point<1>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c, F);
-            else
-              face_pair_point<2>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c, F);
-            nitem = lx + 1 < e0 ? 2 : 1;
-          }
-        } else {
-          face_flux_item(P, g, d, i0 + lx, j0 + ly, k0 + lz, Win, c, F[0]);
-        }
-        for (int h = 0; h < nitem; ++h) {
-          const int li = lx + h + LX * (ly + LY * lz);
-          fd[0 * NF + li] = F[h][0];
-          fd[(1 + d) * NF + li] = F[h][1];
-          fd[(1 + a) * NF + li] = F[h][2];
-          fd[(1 + b) * NF + li] = F[h][3];
-          fd[4 * NF + li] = F[h][4];
-        }
+        T F[5];
+        if (PR && d == 0)
+          face_x_point(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c, F);
+        else
+          face_flux_item(P, g, d, i0 + lx, j0 + ly, k0 + lz, Win, c, F);
+        const int li = lx + LX * (ly + LY * lz);
+        fd[0 * NF + li] = F[0];
+        fd[(1 + d) * NF + li] = F[1];
+        fd[(1 + a) * NF + li] = F[2];
+        fd[(1 + b) * NF + li] = F[3];
+        fd[4 * NF + li] = F[4];
       } else if (!EXT) {
         // edge along e: extents t + 1 along the two transverse directions when active
         const int e = k - 3;
@@ -1233,22 +1132,12 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         const int LX = TX + (e != 0), LY = TY + (e != 1);
         T* ed = e == 0 ? exx : (e == 1 ? ey : ez);
         const int li = lx + LX * (ly + LY * lz);
-        if (PR) {
-          if (e == 0 && TWO) {
-            T E2[2];
-            edge_pair_x_point(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c, E2);
-            ed[li] = E2[0];
-            if (lx + 1 < e0) ed[li + 1] = E2[1];
-          } else if (e == 0) {
-            ed[li] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
-          } else if (e == 1) {
-            ed[li] = edge_px_point<1>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
-          } else {
-            ed[li] = edge_px_point<2>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
-          }
-        } else {
+        if (PR && e == 1)
+          ed[li] = edge_px_point<1>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
+        else if (PR && e == 2)
+          ed[li] = edge_px_point<2>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
+        else
           ed[li] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
-        }
       }
     }
     ex.sync();
