@@ -107,15 +107,18 @@ __global__ __launch_bounds__(BLK) void k_pred(const PatchDev* __restrict__ pt,
 }
 
 // Waves per SIMD that the shared memory of a solver work-group allows (160 KB per compute
-// unit), capped at 3 in FP64 and 4 in FP32; the hint makes the register allocation fit them
-// (paired loads hold four registers each in FP64).
+// unit), capped at 3 in FP64 and 4 in FP32, in whole work-groups (a 512-thread work-group
+// puts 2 waves on each SIMD); the hint makes the register allocation fit them (paired loads
+// hold four registers each in FP64).
 template <typename T, int TX, int TY, int TZ, int FORM>
 struct SolveWaves {
   static constexpr int WG = TileShape<TX, TY, TZ>::THREADS / 64;  // waves per work-group
+  static constexpr int PER = WG >= 4 ? WG / 4 : 1;                 // waves per SIMD per work-group
   static constexpr int LDSB = TileShape<TX, TY, TZ>::template Lds<FORM>::value * (int)sizeof(T);
   static constexpr int BY_LDS = (LDSB > 0 ? (160 * 1024) / LDSB : 8) * WG / 4;
-  static constexpr int CAP = sizeof(T) == 8 ? 3 : 4;
-  static constexpr int value = BY_LDS < 1 ? 1 : (BY_LDS < CAP ? BY_LDS : CAP);
+  static constexpr int CAP = sizeof(T) == 8 ? (PER == 2 ? 4 : 3) : 4;
+  static constexpr int RAW = BY_LDS < CAP ? BY_LDS : CAP;
+  static constexpr int value = RAW / PER * PER < 1 ? 1 : RAW / PER * PER;
 };
 template <typename T, int TX, int TY, int TZ, int FORM>
 __global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS))
