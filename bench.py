@@ -36,7 +36,7 @@ def log(*a):
 # HBM bytes of one FP64 update (every update kernel), measured with rocprofv3 --pmc FETCH_SIZE
 # and WRITE_SIZE on the turbulence workload and scaled by the same counters on a plain
 # 1 GiB device copy (FETCH_SIZE reads 0.5x there, WRITE_SIZE 1x); see profiles/.  Keyed by
-# launch configuration ((tile x, y, z, mode), fused predictor, solver form); valid only for
+# launch configuration ((tile x, y, z, mode), predictor mode, solver form); valid only for
 # the kernel sources it was measured on: reported as null once they change.
 MEASURED_TRAFFIC = {
     "sources_sha256": "7a92d128b0c4718516cd6eb5ae26242e8b1605383960b5590b4f57b6921434ad",
@@ -153,6 +153,7 @@ def run_precision(w, precision, steps, warmup, flops_per_cell, tile=None, predic
         "update_tflops": flops_per_cell * cells / (upd_ms * 1e-3) / 1e12,
         "update_hbm_gbs": bpc * cells / (upd_ms * 1e-3) / 1e9,
         "tile": {"chosen": list(cfgs[best]), "fused_predictor": B.predictor(),
+                 "predictor_tile": list(B.predictor_modes()[B.predictor()]),
                  "solver_split": B.solver_split(),
                  "tuned_ms": {str(list(c)): (None if m != m else round(m, 3))
                               for c, m in zip(cfgs, tune_ms)}},
@@ -349,8 +350,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--tile", type=int, default=None,
                     help="use this launch configuration instead of autotuning")
-    ap.add_argument("--predictor", type=int, default=None, choices=(0, 1),
-                    help="force the staged (0) or fused (1) predictor")
+    ap.add_argument("--predictor", type=int, default=None,
+                    help="force the predictor mode: 0 staged kernels, k >= 1 fused tile kernel "
+                         "with the k-th tile shape (for 3D: 1 = 8x8x4, 2 = 34x4x2)")
     ap.add_argument("--split", type=int, default=None, choices=(0, 1, 2),
                     help="force the solver form: one-phase (0), two-phase (1), edge pass (2)")
     ap.add_argument("--fp32-only", action="store_true",

@@ -150,11 +150,18 @@ int32_t mhd_bunch_tile_current(const mhd_bunch* h);
 mhd_status mhd_bunch_tile_get(const mhd_bunch* h, int32_t index, int32_t cfg[4]);
 mhd_status mhd_bunch_tile_set(mhd_bunch* h, int32_t index);
 
-/* Predictor stages: 0 = three kernels (primitives, edge EMFs at time n, predictor) through
- * the workspace scratch; 1 = one tiled kernel that keeps primitives and EMFs of a tile (plus
- * one cell around it) in shared memory.  Same values either way.  Default 0. */
-mhd_status mhd_bunch_set_predictor(mhd_bunch* h, int32_t fused);
+/* Predictor stages (the half-step prediction of §2.1 "The MUSCL Scheme"): mode 0 = three
+ * kernels (primitives, edge EMFs at time n, predictor) through the workspace scratch;
+ * mode k >= 1 = one tiled kernel that keeps the primitives and face fields of a tile (plus
+ * one cell around it) in shared memory, with the k-th tile shape of the bunch's
+ * dimensionality.  mhd_bunch_predictor_count returns the number of modes (staged + fused
+ * shapes); mhd_bunch_predictor_shape fills tile3 with the tile of a mode ({0, 0, 0} for 0).
+ * Same values in every mode.  Default 0; mhd_bunch_set_predictor returns MHD_EINVAL for a
+ * mode outside [0, count). */
+mhd_status mhd_bunch_set_predictor(mhd_bunch* h, int32_t mode);
 int32_t mhd_bunch_predictor(const mhd_bunch* h);
+int32_t mhd_bunch_predictor_count(const mhd_bunch* h);
+mhd_status mhd_bunch_predictor_shape(const mhd_bunch* h, int32_t mode, int32_t tile3[3]);
 
 /* Solver form: 0 = face fluxes and edge EMFs of the tile held in shared memory together,
  * then the whole update; 1 = two phases (face fluxes, hydro update; then edge EMFs, field
@@ -167,10 +174,10 @@ int32_t mhd_bunch_solver_split(const mhd_bunch* h);
 
 /* Times every configuration, each with every solver form, on the caller's data (one
  * warm-up and `reps` timed updates of U_in -> U_out each, HIP events on `stream`) and keeps
- * the fastest pair; then, with it, times both predictor forms and keeps the faster.
+ * the fastest pair; then, with it, times every predictor mode and keeps the fastest.
  * Synchronises `stream`; overwrites U_out.  best (may be NULL) receives the chosen
  * configuration index, ms (may be NULL, else float[mhd_bunch_tile_count]) the mean update
- * time of each configuration (the faster of its two solver forms). */
+ * time of each configuration (the fastest of its solver forms). */
 mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* U_in, void* U_out, const double* dt_dev,
                               const double* dx_dev, int32_t reps, hipStream_t stream,
                               int32_t* best, float* ms);

@@ -95,6 +95,8 @@ _SIGS = {
     "mhd_bunch_graph_launch": (C.c_int, [_h, _st]),
     "mhd_bunch_set_predictor": (C.c_int, [_h, C.c_int32]),
     "mhd_bunch_predictor": (C.c_int32, [_h]),
+    "mhd_bunch_predictor_count": (C.c_int32, [_h]),
+    "mhd_bunch_predictor_shape": (C.c_int, [_h, C.c_int32, _v]),
     "mhd_bunch_set_solver_split": (C.c_int, [_h, C.c_int32]),
     "mhd_bunch_solver_split": (C.c_int32, [_h]),
 }
@@ -260,11 +262,22 @@ class Bunch:
     def set_tile(self, index):
         _ok(mhd_bunch_tile_set(self._h, int(index)), "mhd_bunch_tile_set")
 
-    def set_predictor(self, fused):
-        _ok(mhd_bunch_set_predictor(self._h, int(bool(fused))), "mhd_bunch_set_predictor")
+    def set_predictor(self, mode):
+        """0 = staged kernels, k >= 1 = fused tile kernel with the k-th predictor shape."""
+        _ok(mhd_bunch_set_predictor(self._h, int(mode)), "mhd_bunch_set_predictor")
 
     def predictor(self):
         return int(mhd_bunch_predictor(self._h))
+
+    def predictor_modes(self):
+        """Tile shape of every predictor mode ((0, 0, 0) for the staged kernels)."""
+        out = []
+        for k in range(int(mhd_bunch_predictor_count(self._h))):
+            t = (C.c_int32 * 3)()
+            _ok(mhd_bunch_predictor_shape(self._h, k, C.cast(t, C.c_void_p)),
+                "mhd_bunch_predictor_shape")
+            out.append(tuple(int(v) for v in t))
+        return out
 
     def set_solver_split(self, form):
         """Solver form: 0 one-phase tile, 1 two-phase tile, 2 separate edge-EMF pass."""

@@ -137,11 +137,19 @@ __attribute__((amdgpu_waves_per_eu(SolveWaves<T, TX, TY, TZ, FORM>::value))) voi
   }
 }
 
-// 256-thread tiles: three work-groups per compute unit fit the shared memory of FP64 tiles;
-// the hint keeps the registers within three waves per SIMD to match
+// Waves per SIMD that the shared memory of a predictor work-group allows, capped at 3 in
+// FP64 and 5 in FP32; the hint keeps the registers within them.
 template <typename T, int PX, int PY, int PZ>
-__global__ __launch_bounds__((PredShape<PX, PY, PZ>::THREADS),
-                             (PredShape<PX, PY, PZ>::THREADS == 256 ? 3 : 1)) void k_predict(
+struct PredWaves {
+  static constexpr int WG = (PredShape<PX, PY, PZ>::THREADS + 63) / 64;
+  static constexpr int PER_CU = (160 * 1024) / (PredShape<PX, PY, PZ>::LDS_ELEMS * (int)sizeof(T));
+  static constexpr int BY_LDS = (PER_CU * WG + 3) / 4;
+  static constexpr int CAP = sizeof(T) == 8 ? 3 : 5;
+  static constexpr int value = BY_LDS < 1 ? 1 : (BY_LDS < CAP ? BY_LDS : CAP);
+};
+template <typename T, int PX, int PY, int PZ>
+__global__ __launch_bounds__((PredShape<PX, PY, PZ>::THREADS))
+__attribute__((amdgpu_waves_per_eu(PredWaves<T, PX, PY, PZ>::value))) void k_predict(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, const T* __restrict__ U,
     T* __restrict__ W, const double* __restrict__ dt, const double* __restrict__ dx, Consts<T> c,
     int g, int* status, int ntile, int remap) {
@@ -350,17 +358,27 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 #define MHD_SHAPES_5(F) F(16, 1, 16)
 #define MHD_SHAPES_2(F) F(1, 64, 1)
 #define MHD_SHAPES_4(F) F(1, 1, 64)
-// fused predictor tile per activity pattern
-#define MHD_PRED_SHAPE(act, F)                \
+// fused predictor tile shapes per activity pattern, the first the default.  A tile as wide
+// as the predictor box of a 32-cell patch (34) stores whole rows, so each wavefront writes
+// one contiguous run of a predictor slot (the compact 8 x 8 x 4 tile has the smaller halo)
+#define MHD_PSHAPES_7(F) F(8, 8, 4) F(34, 4, 2)
+#define MHD_PSHAPES_3(F) F(16, 16, 1) F(34, 8, 1)
+#define MHD_PSHAPES_6(F) F(1, 16, 16)
+#define MHD_PSHAPES_5(F) F(16, 1, 16)
+#define MHD_PSHAPES_1(F) F(128, 1, 1)
+#define MHD_PSHAPES_2(F) F(1, 128, 1)
+#define MHD_PSHAPES_4(F) F(1, 1, 128)
+#define MHD_PRED_SHAPES(act, F)               \
   switch (act) {                               \
-    case 7: F(8, 8, 4) break;                  \
-    case 3: F(16, 16, 1) break;                \
-    case 6: F(1, 16, 16) break;                \
-    case 5: F(16, 1, 16) break;                \
-    case 1: F(128, 1, 1) break;                \
-    case 2: F(1, 128, 1) break;                \
-    default: F(1, 1, 128) break;               \
+    case 7: MHD_PSHAPES_7(F) break;            \
+    case 3: MHD_PSHAPES_3(F) break;            \
+    case 6: MHD_PSHAPES_6(F) break;            \
+    case 5: MHD_PSHAPES_5(F) break;            \
+    case 1: MHD_PSHAPES_1(F) break;            \
+    case 2: MHD_PSHAPES_2(F) break;            \
+    default: MHD_PSHAPES_4(F) break;           \
   }
+constexpr int MAXPSHAPE = 4;
 constexpr int MAXSHAPE = 8;
 constexpr int NMODE = 3;  // launch modes per tile shape: plain grid, XCD remap, persistent
 struct TileCand {
@@ -382,7 +400,7 @@ struct mhd_bunch {
     int p0 = 0, p1 = 0;
     int blk0[NBOX] = {0}, nblk[NBOX] = {0};
     int tile0[MAXSHAPE] = {0}, ntile[MAXSHAPE] = {0};
-    int ptile0 = 0, nptile = 0;
+    int ptile0[MAXPSHAPE] = {0}, nptile[MAXPSHAPE] = {0};
     int blk0_all = 0, nblk_all = 0;  // range of the whole-bunch BOX_ALL table
   };
   std::vector<Chunk> chunks;
@@ -393,12 +411,14 @@ struct mhd_bunch {
   int ncu = 256;                           // compute units of the bound device
   TileCand shapes[MAXSHAPE];
   std::vector<TileDev> tiles[MAXSHAPE];
-  // fused predictor (mhd_bunch_set_predictor): tile table over the predictor boxes
+  // predictor (mhd_bunch_set_predictor): 0 staged kernels, k >= 1 fused with tile shape
+  // pshapes[k - 1]; one tile table over the predictor boxes per fused shape
   int fused = 0;
   int split = 0;  // solver form (mhd_bunch_set_solver_split): 0 one-phase, 1 two-phase, 2 edge pass
-  int PXs = 8, PYs = 8, PZs = 4;
-  std::vector<TileDev> ptiles;
-  size_t o_ptiles = 0;
+  int npshape = 0;
+  TileCand pshapes[MAXPSHAPE];
+  std::vector<TileDev> ptiles[MAXPSHAPE];
+  size_t o_ptiles[MAXPSHAPE] = {0};
   int64_t scratch_elems = 0;
   size_t o_pt = 0, o_blk[NBOX] = {0}, o_tiles[MAXSHAPE] = {0}, o_smax = 0, o_status = 0,
          o_scratch = 0;
@@ -484,7 +504,7 @@ struct mhd_bunch {
   const PatchDev* d_pt() const { return (const PatchDev*)(ws + o_pt); }
   const BoxBlock* d_blk(int k) const { return (const BoxBlock*)(ws + o_blk[k]); }
   const TileDev* d_tiles(int k) const { return (const TileDev*)(ws + o_tiles[k]); }
-  const TileDev* d_ptiles() const { return (const TileDev*)(ws + o_ptiles); }
+  const TileDev* d_ptiles(int k) const { return (const TileDev*)(ws + o_ptiles[k]); }
   unsigned long long* d_smax() const { return (unsigned long long*)(ws + o_smax); }
   int* d_status() const { return (int*)(ws + o_status); }
   void* d_scratch() const { return ws + o_scratch; }
@@ -587,12 +607,14 @@ mhd_status launch_update(mhd_bunch* h, const T* Uin, T* Uout, const double* dt, 
   const int rm = h->mode >= 1;
   for (const auto& ch : h->chunks) {
     hipEvent_t t0;
-    if (h->fused && ch.nptile) {
+    if (h->fused && ch.nptile[h->fused - 1]) {
       t0 = h->tic(s);
-      const int nt = ch.nptile;
-      const TileDev* tl = h->d_ptiles() + ch.ptile0;
+      const int pk = h->fused - 1;
+      const TileCand pc = h->pshapes[pk];
+      const int nt = ch.nptile[pk];
+      const TileDev* tl = h->d_ptiles(pk) + ch.ptile0[pk];
 #define MHD_PRED_LAUNCH(X, Y, Z)                                                                \
-  {                                                                                            \
+  if (pc.x == X && pc.y == Y && pc.z == Z) {                                                   \
     int grid = nt;                                                                             \
     if (h->mode == 2) {                                                                        \
       int occ = 0;                                                                             \
@@ -605,7 +627,7 @@ mhd_status launch_update(mhd_bunch* h, const T* Uin, T* Uout, const double* dt, 
     hipLaunchKernelGGL((k_predict<T, X, Y, Z>), dim3(grid), dim3(PredShape<X, Y, Z>::THREADS), 0, \
                        s, h->d_pt(), tl, Uin, S, dt, dx, c, h->g, h->d_status(), nt, rm);      \
   }
-      MHD_PRED_SHAPE(h->act, MHD_PRED_LAUNCH)
+      MHD_PRED_SHAPES(h->act, MHD_PRED_LAUNCH)
 #undef MHD_PRED_LAUNCH
       h->toc(s, MHD_KERNEL_PREDICT, t0);
     }
@@ -853,9 +875,10 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
   }
   h->state_elems = base;
   set_shapes(h);
-#define MHD_SET_PRED(X, Y, Z) { h->PXs = X; h->PYs = Y; h->PZs = Z; }
-  MHD_PRED_SHAPE(h->act, MHD_SET_PRED)
-#undef MHD_SET_PRED
+  h->npshape = 0;
+#define MHD_ADD_PRED(X, Y, Z) h->pshapes[h->npshape++] = TileCand{X, Y, Z};
+  MHD_PRED_SHAPES(h->act, MHD_ADD_PRED)
+#undef MHD_ADD_PRED
 
   // chunks of consecutive patches whose scratch fits the cap
   const int64_t esz = h->prec;
@@ -905,18 +928,21 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
       }
       ch.ntile[k] = (int)h->tiles[k].size() - ch.tile0[k];
     }
-    ch.ptile0 = (int)h->ptiles.size();
-    for (int p = ch.p0; p < ch.p1; ++p) {
-      const PatchDev& P = h->pt[p];
-      const int T3[3] = {h->PXs, h->PYs, h->PZs};
-      int nt[3];
-      for (int dd = 0; dd < 3; ++dd) nt[dd] = (P.act >> dd & 1) ? (P.n[dd] + 2 + T3[dd] - 1) / T3[dd] : 1;
-      for (int z = 0; z < nt[2]; ++z)
-        for (int y = 0; y < nt[1]; ++y)
-          for (int x = 0; x < nt[0]; ++x)
-            h->ptiles.push_back(TileDev{p, x * T3[0], y * T3[1], z * T3[2]});
+    for (int k = 0; k < h->npshape; ++k) {
+      const TileCand pc = h->pshapes[k];
+      const int T3[3] = {pc.x, pc.y, pc.z};
+      ch.ptile0[k] = (int)h->ptiles[k].size();
+      for (int p = ch.p0; p < ch.p1; ++p) {
+        const PatchDev& P = h->pt[p];
+        int nt[3];
+        for (int dd = 0; dd < 3; ++dd) nt[dd] = (P.act >> dd & 1) ? (P.n[dd] + 2 + T3[dd] - 1) / T3[dd] : 1;
+        for (int z = 0; z < nt[2]; ++z)
+          for (int y = 0; y < nt[1]; ++y)
+            for (int x = 0; x < nt[0]; ++x)
+              h->ptiles[k].push_back(TileDev{p, x * T3[0], y * T3[1], z * T3[2]});
+      }
+      ch.nptile[k] = (int)h->ptiles[k].size() - ch.ptile0[k];
     }
-    ch.nptile = (int)h->ptiles.size() - ch.ptile0;
   }
   for (auto& ch : h->chunks) {
     ch.blk0_all = (int)h->blocks[BOX_ALL].size();
@@ -939,8 +965,10 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
     h->o_tiles[k] = o;
     o = align256(o + sizeof(TileDev) * std::max<size_t>(1, h->tiles[k].size()));
   }
-  h->o_ptiles = o;
-  o = align256(o + sizeof(TileDev) * std::max<size_t>(1, h->ptiles.size()));
+  for (int k = 0; k < h->npshape; ++k) {
+    h->o_ptiles[k] = o;
+    o = align256(o + sizeof(TileDev) * std::max<size_t>(1, h->ptiles[k].size()));
+  }
   h->o_smax = o;
   o = align256(o + sizeof(unsigned long long) * h->P);
   h->o_status = o;
@@ -979,9 +1007,10 @@ mhd_status mhd_bunch_bind(mhd_bunch* h, void* ws, hipStream_t s) {
       ok = h->hip_ok(hipMemcpyAsync(h->ws + h->o_blk[k], h->blocks[k].data(),
                                     sizeof(BoxBlock) * h->blocks[k].size(), hipMemcpyHostToDevice, s),
                      "upload block table");
-  if (ok && !h->ptiles.empty())
-    ok = h->hip_ok(hipMemcpyAsync(h->ws + h->o_ptiles, h->ptiles.data(),
-                                  sizeof(TileDev) * h->ptiles.size(), hipMemcpyHostToDevice, s),
+  for (int k = 0; k < h->npshape; ++k)
+    if (ok && !h->ptiles[k].empty())
+      ok = h->hip_ok(hipMemcpyAsync(h->ws + h->o_ptiles[k], h->ptiles[k].data(),
+                                    sizeof(TileDev) * h->ptiles[k].size(), hipMemcpyHostToDevice, s),
                    "upload predictor tile table");
   for (int k = 0; k < h->nshape && ok; ++k)
     if (!h->tiles[k].empty())
@@ -1133,13 +1162,27 @@ mhd_status mhd_bunch_tile_set(mhd_bunch* h, int32_t idx) {
   return MHD_OK;
 }
 
-mhd_status mhd_bunch_set_predictor(mhd_bunch* h, int32_t fused) {
-  if (!h || (fused != 0 && fused != 1)) return MHD_EINVAL;
-  h->fused = fused;
+mhd_status mhd_bunch_set_predictor(mhd_bunch* h, int32_t mode) {
+  if (!h || mode < 0 || mode > h->npshape) return MHD_EINVAL;
+  h->fused = mode;
   return MHD_OK;
 }
 
 int32_t mhd_bunch_predictor(const mhd_bunch* h) { return h ? h->fused : -1; }
+
+int32_t mhd_bunch_predictor_count(const mhd_bunch* h) { return h ? h->npshape + 1 : -1; }
+
+mhd_status mhd_bunch_predictor_shape(const mhd_bunch* h, int32_t mode, int32_t* tile3) {
+  if (!h || !tile3 || mode < 0 || mode > h->npshape) return MHD_EINVAL;
+  if (mode == 0) {
+    tile3[0] = tile3[1] = tile3[2] = 0;
+  } else {
+    tile3[0] = h->pshapes[mode - 1].x;
+    tile3[1] = h->pshapes[mode - 1].y;
+    tile3[2] = h->pshapes[mode - 1].z;
+  }
+  return MHD_OK;
+}
 
 mhd_status mhd_bunch_set_solver_split(mhd_bunch* h, int32_t split) {
   if (!h || split < 0 || split > 2) return MHD_EINVAL;
@@ -1197,12 +1240,18 @@ mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* Uin, void* Uout, const d
   h->mode = bi % NMODE;
   h->split = bsplit;
   const int f0 = h->fused;
-  float fms[2] = {0.0f, 0.0f};
-  for (int f = 0; f < 2 && ok; ++f) {
+  int fbest = 0;
+  float fbms = 0.0f;
+  for (int f = 0; f <= h->npshape && ok; ++f) {
     h->fused = f;
-    time_it(&fms[f]);
+    float t = 0.0f;
+    time_it(&t);
+    if (f == 0 || t < fbms) {
+      fbest = f;
+      fbms = t;
+    }
   }
-  h->fused = ok ? (fms[1] < fms[0] ? 1 : 0) : f0;
+  h->fused = ok ? fbest : f0;
   if (a) (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
   h->prof = prof;

@@ -95,6 +95,33 @@ def test_scratch_cap_bounds_the_workspace(B):
         B.mhd_bunch_destroy(h2)
 
 
+@pytest.mark.parametrize("dims,shapes", [
+    ([[32, 32, 32]] * 2, [(0, 0, 0), (8, 8, 4), (34, 4, 2)]),
+    ([[32, 32, 1]] * 2, [(0, 0, 0), (16, 16, 1), (34, 8, 1)]),
+    ([[64, 1, 1]] * 2, [(0, 0, 0), (128, 1, 1)]),
+    ([[1, 16, 16]], [(0, 0, 0), (1, 16, 16)]),
+])
+def test_predictor_modes_are_listed_and_range_checked(B, dims, shapes):
+    rc, h = _create(B, dims)
+    assert rc == B.MHD_OK
+    try:
+        n = B.mhd_bunch_predictor_count(h)
+        assert n == len(shapes)
+        for k, want in enumerate(shapes):
+            t = (C.c_int32 * 3)()
+            assert B.mhd_bunch_predictor_shape(h, k, C.cast(t, C.c_void_p)) == B.MHD_OK
+            assert tuple(t) == want
+        t = (C.c_int32 * 3)()
+        assert B.mhd_bunch_predictor_shape(h, n, C.cast(t, C.c_void_p)) == B.MHD_EINVAL
+        assert B.mhd_bunch_predictor(h) == 0
+        for bad in (-1, n):
+            assert B.mhd_bunch_set_predictor(h, bad) == B.MHD_EINVAL
+        assert B.mhd_bunch_set_predictor(h, n - 1) == B.MHD_OK
+        assert B.mhd_bunch_predictor(h) == n - 1
+    finally:
+        B.mhd_bunch_destroy(h)
+
+
 def test_status_strings(B):
     for code in range(-6, 1):
         assert B.mhd_status_string(code)

@@ -240,7 +240,7 @@ def test_chunked_scratch_gives_identical_results():
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("fused", [0, 1])
+@pytest.mark.parametrize("fused", [0, 1, 2])
 def test_nonphysical_state_is_reported(fused):
     log(f"[gpu] non-physical flag, predictor {fused}")
     L, U, dx, nbr, gam = _case("ot64")
