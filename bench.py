@@ -39,14 +39,17 @@ def log(*a):
 # launch configuration ((tile x, y, z, mode), predictor mode, solver form); valid only for
 # the kernel sources it was measured on: reported as null once they change.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "7a92d128b0c4718516cd6eb5ae26242e8b1605383960b5590b4f57b6921434ad",
+    "sources_sha256": "e7a39ce12747630e70824d284588db1a9419bd444f2351231ba344b88b9446d8",
     "bytes_per_update": {
-        "[32, 4, 2, 1]/1/0": 199.88e9,
-        "[32, 4, 4, 1]/1/0": 168.91e9,
-        "[32, 8, 2, 1]/1/0": 166.05e9,
-        "[32, 4, 2, 1]/1/1": 196.41e9,
-        "[32, 4, 4, 1]/1/1": 174.13e9,
-        "[32, 8, 2, 1]/1/1": 170.85e9,
+        "[32, 4, 2, 1]/1/0": 198.69e9,
+        "[32, 4, 4, 1]/1/0": 168.48e9,
+        "[32, 8, 2, 1]/1/0": 166.44e9,
+        "[32, 4, 2, 1]/1/1": 196.67e9,
+        "[32, 4, 4, 1]/1/1": 229.07e9,
+        "[32, 8, 2, 1]/1/1": 231.19e9,
+        "[32, 4, 2, 1]/1/2": 233.49e9,
+        "[32, 4, 4, 1]/1/2": 228.69e9,
+        "[32, 8, 2, 1]/1/2": 225.73e9,
     },
     "profile": "profiles/mhd_update_turbulence512_pmc.md",
 }
