@@ -177,7 +177,8 @@ int32_t mhd_bunch_solver_split(const mhd_bunch* h);
  * the fastest pair; then, with it, times every predictor mode and keeps the fastest.
  * Synchronises `stream`; overwrites U_out.  best (may be NULL) receives the chosen
  * configuration index, ms (may be NULL, else float[mhd_bunch_tile_count]) the mean update
- * time of each configuration (the fastest of its solver forms). */
+ * time of each configuration (the fastest of its solver forms).  On an error the
+ * configuration, solver form and predictor mode stay as they were before the call. */
 mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* U_in, void* U_out, const double* dt_dev,
                               const double* dx_dev, int32_t reps, hipStream_t stream,
                               int32_t* best, float* ms);

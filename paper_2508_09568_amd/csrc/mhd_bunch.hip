@@ -1,14 +1,21 @@
 // mhd_bunch.hip -- kernels and C ABI of the ideal-MHD bunch update for gfx950.
 //
-// One update of a chunk of patches runs four kernels on the caller's stream:
-//   k_prim  : primitives on every padded cell                      (box [0, N-1))
-//   k_en    : edge EMFs at time n from 4-cell / 2-face averages      (box [1, N-1))
-//   k_pred  : limited slopes, half-step state, half-step face field,
-//             transverse face-field slopes on the cells around the interior
-//   k_solve : per 3D tile, HLLD on every face and the four-state EMF on every edge into
-//             shared memory, then the conservative + constrained-transport update.
-// Side kernels: k_cfl (per-patch time step, wavefront max-reduction + one 64-bit atomic
-// per work-group), k_guards (guard fill from a neighbour table).
+// One update of a chunk of patches runs on the caller's stream:
+//   predictor, staged (predictor mode 0), three kernels over flat block tables:
+//     k_prim    : primitives on every padded cell                    (box [0, N-1))
+//     k_en      : edge EMFs at time n from 4-cell / 2-face averages    (box [1, N-1))
+//     k_pred    : limited slopes, half-step state, half-step face field,
+//                 transverse face-field slopes on the cells around the interior
+//   predictor, fused (modes >= 1): k_predict does the three steps per 3D tile, with the
+//               tile's primitives and face fields in shared memory and the edge EMFs at
+//               time n evaluated from them where they are read
+//   k_edges   : (solver form 2 only) half-step edge EMFs, each edge once, into scratch
+//   k_solve   : per 3D tile, HLLD on every face and the four-state EMF on every edge (or
+//               the EMFs k_edges left) into shared memory, then the conservative +
+//               constrained-transport update.
+// Side kernels: k_cfl / k_cfl_final (per-patch time step, wavefront max-reduction + one
+// 64-bit atomic per work-group), k_guards (guard fill from a neighbour table), and the
+// k_adj_* reverse sweep of the adjoint, which re-runs the staged predictor kernels first.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1214,6 +1221,7 @@ mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* Uin, void* Uout, const d
   };
   // tile shape x launch mode x solver form, jointly (the two-phase and edge-pass forms are
   // what let the larger tiles fit), then the predictor form with the winner
+  const int shape0 = h->shape, mode0 = h->mode, split0 = h->split;
   int bi = 0, bsplit = 0;
   float bms = 0.0f;
   bool first = true;
@@ -1252,6 +1260,11 @@ mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* Uin, void* Uout, const d
     }
   }
   h->fused = ok ? fbest : f0;
+  if (!ok) {  // a failed run leaves the configuration the caller had
+    h->shape = shape0;
+    h->mode = mode0;
+    h->split = split0;
+  }
   if (a) (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
   h->prof = prof;
