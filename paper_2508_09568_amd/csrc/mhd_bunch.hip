@@ -877,6 +877,11 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
     P.woff[1] = (act & 2) ? Nw[0] : 0;
     P.woff[2] = (act & 4) ? (int64_t)Nw[0] * Nw[1] : 0;
     P.Nwc = (int64_t)Nw[0] * Nw[1] * Nw[2];
+    // the kernels address a patch's scratch block by 32-bit byte offsets from its base
+    if ((11 * P.Nc + NW * P.Nwc) * (int64_t)h->prec > (int64_t)UINT32_MAX) {
+      delete h;
+      return MHD_EUNSUPPORTED;
+    }
     P.ubase = base;
     base += 8 * P.Nc;
   }
