@@ -257,22 +257,36 @@ def test_nonphysical_state_is_reported(fused):
 
 
 def _sampled_parity(w, precision, samples, dt_local, tol, tune=False):
-    """One update of a full-size workload on the GPU; the oracle recomputes the sampled
-    patches from the GPU's own input (guards included).  tune: first run the autotuner on
-    these buffers, as the benchmark does, so the update runs in the launch configuration
-    (tile shape, launch mode, predictor and solver form) the benchmark times."""
+    """One update of a full-size workload on the GPU against the oracle on sampled patches.
+    Both sides start from the generator's state, rounded to the GPU's precision: the oracle
+    fills the guards and takes the time step on its own host copy, the GPU does both with its
+    kernels and they are checked against the oracle's (guards bitwise, dt to rounding), and
+    both updates then use the oracle's dt.  tune: first run the autotuner on these buffers,
+    as the benchmark does, so the update runs in the launch configuration (tile shape, launch
+    mode, predictor and solver form) the benchmark times."""
     import oracle
     import torch
     L = w.layout
-    prm = oracle.Params(gamma=w.gamma)
-    B = make_bunch(L, w.gamma, precision=precision)
+    prm = oracle.Params(gamma=w.gamma, cfl=w.cfl)
     dtype = torch.float64 if precision == 8 else torch.float32
+    # oracle side: the generator's state as the GPU holds it, in float64, on the host
+    Ur = w.U.cpu().to(dtype).double().numpy()
+    if w.nbr is not None:
+        oracle.fill_guards(Ur, L.dims, L.g, w.nbr)
+    dto = oracle.cfl_many(Ur, L.dims, L.g, w.dx, prm)
+    if not dt_local:
+        dto = np.full(L.P, dto.min())
+    # GPU side
+    B = make_bunch(L, w.gamma, precision=precision, cfl=w.cfl)
     Ui = w.U.to(device="cuda", dtype=dtype)
     dxd = dev(w.dx)
     if w.nbr is not None:
         B.fill_guards(Ui, dev(w.nbr.astype(np.int32)))
-    dt = torch.zeros(L.P, dtype=torch.float64, device="cuda")
-    B.cfl(Ui, dxd, dt, global_min=not dt_local)
+    dtg = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    B.cfl(Ui, dxd, dtg, global_min=not dt_local)
+    # time step of the FP32 state: FP32 arithmetic, a few dozen roundings of 6e-8
+    np.testing.assert_allclose(host(dtg), dto, rtol=1e-13 if precision == 8 else 1e-5, atol=0)
+    dt = dev(dto)
     Uo = torch.empty_like(Ui)
     if tune:
         best, _ = B.autotune(Ui, Uo, dt, dxd, reps=2)
@@ -280,13 +294,12 @@ def _sampled_parity(w, precision, samples, dt_local, tol, tune=False):
             f"solver form {B.solver_split()}")
     B.update(Ui, Uo, dt, dxd)
     assert B.check() == 0
-    dth = host(dt)
     worst = np.zeros(8)
     for p in samples:
         a, b = int(L.base[p]), int(L.base[p + 1])
-        Up = Ui[a:b].double().cpu().numpy()
+        assert np.array_equal(Ui[a:b].double().cpu().numpy(), Ur[a:b]), f"guards of patch {p}"
         n = L.dims[p]
-        ref = oracle.step_many(Up, n[None], L.g, [dth[p]], w.dx[p][None], prm)
+        ref = oracle.step_many(Ur[a:b], n[None], L.g, [dto[p]], w.dx[p][None], prm)
         got = Uo[a:b].double().cpu().numpy()
         Lp = W.Layout(n[None], L.g)
         worst = np.maximum(worst, rel_err_fields(Lp, got, ref))
