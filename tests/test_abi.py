@@ -52,6 +52,7 @@ def _create(B, dims, **kw):
     (dict(), [[2, 16, 16]]),                  # an active direction narrower than g
     (dict(), [[16, 0, 16]]),
     (dict(rho_floor=0.0), [[16, 16, 16]]),
+    (dict(), np.zeros((0, 3))),               # no patches
 ])
 def test_create_rejects_invalid_descriptions(B, kw, dims):
     rc, h = _create(B, dims, **kw)

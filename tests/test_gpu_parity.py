@@ -332,6 +332,17 @@ def test_uneven_full_size_sampled_fp64():
     _sampled_parity(w, 8, samples, dt_local=True, tol=FP64_STEP_TOL)
 
 
+@pytest.mark.parametrize("precision,n,tune", [(8, 219, False), (8, 219, True), (4, 276, True)])
+def test_largest_patch_matches_oracle(precision, n, tune):
+    """One periodic patch at the largest size the library accepts, its scratch block just
+    under 4 GiB (the kernels address it by 32-bit byte offsets): guard fill, time step and
+    one update against the oracle on every cell, in the default and the tuned configuration."""
+    log(f"[gpu] largest patch {n}^3, precision {precision}, tuned {tune}")
+    w = W.turbulence(N=n, patch=n, device="cuda")
+    _sampled_parity(w, precision, [0], dt_local=False,
+                    tol=FP64_STEP_TOL if precision == 8 else 2e-5, tune=tune)
+
+
 def test_adjoint_case_20_steps_fp64():
     import oracle
     log("[gpu] adjoint case 64^3 (8 x 32^3) fp64, 20 steps at fixed dt")
