@@ -387,6 +387,25 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
   }
 constexpr int MAXPSHAPE = 4;
 constexpr int MAXSHAPE = 8;
+// every shape list fits the fixed-size tables of the handle
+#define MHD_COUNT_SHAPE(X, Y, Z) +1
+static_assert(0 MHD_PSHAPES_7(MHD_COUNT_SHAPE) <= MAXPSHAPE &&
+              0 MHD_PSHAPES_3(MHD_COUNT_SHAPE) <= MAXPSHAPE &&
+              0 MHD_PSHAPES_6(MHD_COUNT_SHAPE) <= MAXPSHAPE &&
+              0 MHD_PSHAPES_5(MHD_COUNT_SHAPE) <= MAXPSHAPE &&
+              0 MHD_PSHAPES_1(MHD_COUNT_SHAPE) <= MAXPSHAPE &&
+              0 MHD_PSHAPES_2(MHD_COUNT_SHAPE) <= MAXPSHAPE &&
+              0 MHD_PSHAPES_4(MHD_COUNT_SHAPE) <= MAXPSHAPE,
+              "a predictor shape list exceeds MAXPSHAPE");
+static_assert(0 MHD_SHAPES_7(MHD_COUNT_SHAPE) <= MAXSHAPE &&
+              0 MHD_SHAPES_3(MHD_COUNT_SHAPE) <= MAXSHAPE &&
+              0 MHD_SHAPES_6(MHD_COUNT_SHAPE) <= MAXSHAPE &&
+              0 MHD_SHAPES_5(MHD_COUNT_SHAPE) <= MAXSHAPE &&
+              0 MHD_SHAPES_1(MHD_COUNT_SHAPE) <= MAXSHAPE &&
+              0 MHD_SHAPES_2(MHD_COUNT_SHAPE) <= MAXSHAPE &&
+              0 MHD_SHAPES_4(MHD_COUNT_SHAPE) <= MAXSHAPE,
+              "a solver shape list exceeds MAXSHAPE");
+#undef MHD_COUNT_SHAPE
 constexpr int NMODE = 3;  // launch modes per tile shape: plain grid, XCD remap, persistent
 struct TileCand {
   int x, y, z;
