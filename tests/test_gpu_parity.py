@@ -155,6 +155,114 @@ def _gpu_run(B, L, U, dx, nbr, t_end=None, nsteps=None, dt_seq=None):
     return host(Ua), np.array(dts)
 
 
+def _uniform_state(L, rho, u, p, B, gam):
+    U = np.zeros(L.total)
+    for q in range(L.P):
+        V = L.view(U, q)
+        V[0] = rho
+        V[1:4] = (rho * u)[:, None, None, None]
+        V[4] = p / (gam - 1) + 0.5 * rho * u @ u + 0.5 * B @ B
+        V[5:8] = B[:, None, None, None]
+    return U
+
+
+def _degenerate_case(name):
+    """Special states of the method: a free stream (every flux and EMF difference is zero), a
+    field-free flow (HLLD's Alfven waves collapse onto the contact), supersonic flow along
+    +(1, 1/2, 1/4) or its reverse (every face and corner fully upwinded), and a stationary
+    contact (an exact steady state)."""
+    gam = 5.0 / 3.0
+    rng = np.random.default_rng(11)
+    if name == "contact":
+        n = 64
+        L = W.Layout([[n, 1, 1]], 3)
+        U = np.zeros(L.total)
+        V = L.view(U, 0)
+        x = (np.arange(n + 6) - 3 + 0.5) / n
+        B = np.array([0.8, 0.5, -0.3])
+        V[0, 0, 0] = np.where((x > 0.25) & (x < 0.75), 2.0, 0.5)
+        V[4, 0, 0] = 1.0 / (gam - 1) + 0.5 * B @ B
+        V[5:8, 0, 0] = B[:, None]
+        return L, U, np.array([[1 / n, 1, 1]]), W.grid_neighbours((1, 1, 1), (True,) * 3), gam
+    if name == "zero_field":
+        w = W.turbulence(N=32, patch=16, mach=1.0)
+        L, U = w.layout, w.U.numpy().copy()
+        for q in range(L.P):
+            V = L.view(U, q)
+            V[4] -= 0.5 * (V[5] ** 2 + V[6] ** 2 + V[7] ** 2)  # uniform face field = cell value
+            V[5:8] = 0.0
+        return L, U, w.dx, w.nbr, w.gamma
+    L = W.Layout([[8, 8, 8]] * 8, 3)
+    nbr = W.grid_neighbours((2, 2, 2), (True, True, True))
+    dx = np.full((L.P, 3), 1 / 16)
+    if name == "free_stream":
+        U = _uniform_state(L, 1.3, np.array([0.7, -0.4, 0.25]), 0.8,
+                           np.array([0.6, -0.9, 0.35]), gam)
+        return L, U, dx, nbr, gam
+    sgn = 1.0 if name == "supersonic_plus" else -1.0
+    u = sgn * np.array([3.0, 1.5, 0.75])            # sound speed 0.13, fast speed < 0.2
+    B = np.array([0.05, 0.02, -0.03])
+    U = _uniform_state(L, 1.0, u, 0.01, B, gam)
+    for q in range(L.P):                            # 1 % density and pressure noise
+        V = L.view(U, q)
+        f = 1.0 + 0.01 * rng.standard_normal(V[0].shape)
+        ke = 0.5 * (V[1] ** 2 + V[2] ** 2 + V[3] ** 2) / V[0]
+        V[4] = (V[4] - ke - 0.5 * B @ B) * (2.0 - f) + ke * f + 0.5 * B @ B
+        V[0:4] *= f
+    return L, U, dx, nbr, gam
+
+
+@pytest.mark.parametrize("name,precision", [
+    ("free_stream", 8), ("free_stream", 4), ("zero_field", 8), ("supersonic_plus", 8),
+    ("supersonic_minus", 8), ("contact", 8)])
+def test_degenerate_states_match_oracle(name, precision):
+    """Five steps of each special state against the oracle's five steps; the free stream
+    and the stationary contact must also stay what they were (bitwise for the free
+    stream, in either precision)."""
+    import oracle
+    log(f"[gpu] degenerate state {name}, precision {precision}")
+    L, U, dx, nbr, gam = _degenerate_case(name)
+    U = np.ascontiguousarray(U)
+    if precision == 4:
+        U = U.astype(np.float32).astype(np.float64)
+    prm = oracle.Params(gamma=gam)
+    U0 = U.copy()
+    oracle.fill_guards(U0, L.dims, L.g, nbr)
+    ref = oracle.run(U0, L.dims, L.g, dx, nbr, prm, nsteps=5)
+    B = make_bunch(L, gam, precision=precision)
+    got, _ = _gpu_run(B, L, U0, dx, nbr, nsteps=5)
+    if name == "free_stream":
+        assert np.array_equal(ref, U0)
+        assert np.array_equal(got, U0)
+        return
+    if name == "contact":
+        np.testing.assert_allclose(L.interior(got, 0), L.interior(U0, 0), rtol=0, atol=1e-13)
+    if name == "zero_field":                        # every EMF is exactly zero
+        assert all(not L.interior(got, p)[5:8].any() for p in range(L.P))
+    err = rel_err_fields(L, got, ref)
+    log(f"    5 steps vs oracle: {err.max():.2e}")
+    assert err.max() <= 5 * FP64_STEP_TOL, err
+
+
+def test_zero_time_step_returns_the_input():
+    """dt = 0: every predicted state is the cell state and every increment is multiplied by
+    zero, so the update copies the interior exactly."""
+    import torch
+    log("[gpu] zero time step")
+    w = W.turbulence(N=32, patch=16)
+    L = w.layout
+    for precision, dtype in ((8, torch.float64), (4, torch.float32)):
+        B = make_bunch(L, w.gamma, precision=precision)
+        Ui = w.U.to(device="cuda", dtype=dtype)
+        B.fill_guards(Ui, dev(w.nbr.astype(np.int32)))
+        Uo = torch.zeros_like(Ui)
+        B.update(Ui, Uo, torch.zeros(L.P, dtype=torch.float64, device="cuda"), dev(w.dx))
+        assert B.check() == 0
+        a, b = Ui.double().cpu().numpy(), Uo.double().cpu().numpy()
+        for p in range(L.P):
+            assert np.array_equal(L.interior(b, p), L.interior(a, p))
+
+
 def test_sod_full_run_fp64_matches_oracle():
     import oracle
     log("[gpu] sod full run fp64")
