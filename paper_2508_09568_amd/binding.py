@@ -170,7 +170,8 @@ class Bunch:
         self.state_elems = int(mhd_bunch_state_elems(h))
         self.workspace = torch.empty(int(mhd_bunch_workspace_bytes(h)), dtype=torch.uint8,
                                      device=self.device)
-        assert self.workspace.data_ptr() % 256 == 0
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace allocation is not 256-byte aligned")
         _ok(mhd_bunch_bind(h, _ptr(self.workspace), _stream(stream)), "mhd_bunch_bind", h)
 
     def __del__(self):
@@ -186,23 +187,50 @@ class Bunch:
     def patch_offset(self, p):
         return int(mhd_bunch_patch_offset(self._h, p))
 
-    def _check_state(self, U):
-        assert U.is_contiguous() and U.dtype == self.dtype and U.numel() == self.state_elems
-        assert U.device == self.device
+    # The library sees plain pointers: every buffer is checked here (type, element count,
+    # layout, device) so that a wrong tensor raises instead of being read out of bounds.
+    def _check(self, t, dtype, n, what):
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{what}: a torch tensor is required, got {type(t).__name__}")
+        if t.dtype != dtype or t.numel() != n or not t.is_contiguous() or t.device != self.device:
+            raise ValueError(f"{what}: a contiguous {dtype} tensor of {n} elements on "
+                             f"{self.device} is required, got {t.dtype} {tuple(t.shape)} on "
+                             f"{t.device}{'' if t.is_contiguous() else ', not contiguous'}")
+
+    def _check_state(self, U, what="state"):
+        self._check(U, self.dtype, self.state_elems, what)
+
+    def _check_dt(self, dt):
+        import torch
+        self._check(dt, torch.float64, self.P, "dt")
+
+    def _check_dx(self, dx):
+        import torch
+        self._check(dx, torch.float64, 3 * self.P, "dx")
+
+    def _check_nbr(self, nbr):
+        import torch
+        self._check(nbr, torch.int32, 27 * self.P, "nbr")
 
     def update(self, U_in, U_out, dt, dx, stream=None):
-        self._check_state(U_in)
-        self._check_state(U_out)
+        self._check_state(U_in, "U_in")
+        self._check_state(U_out, "U_out")
+        self._check_dt(dt)
+        self._check_dx(dx)
         _ok(mhd_bunch_update(self._h, _ptr(U_in), _ptr(U_out), _ptr(dt), _ptr(dx), _stream(stream)),
             "mhd_bunch_update", self._h)
 
     def cfl(self, U, dx, dt_out, global_min=False, stream=None):
         self._check_state(U)
+        self._check_dx(dx)
+        self._check_dt(dt_out)
         _ok(mhd_bunch_cfl(self._h, _ptr(U), _ptr(dx), _ptr(dt_out), int(bool(global_min)),
                           _stream(stream)), "mhd_bunch_cfl", self._h)
 
     def fill_guards(self, U, nbr, stream=None):
         self._check_state(U)
+        self._check_nbr(nbr)
         _ok(mhd_bunch_fill_guards(self._h, _ptr(U), _ptr(nbr), _stream(stream)),
             "mhd_bunch_fill_guards", self._h)
 
@@ -226,8 +254,10 @@ class Bunch:
 
     def adjoint(self, U_in, lam_out, lam_in, dt, dx, stream=None):
         """lam_in = (dU_out/dU_in)^T lam_out for one update at fixed dt (U_in guards filled)."""
-        for t in (U_in, lam_out, lam_in):
-            self._check_state(t)
+        for t, what in ((U_in, "U_in"), (lam_out, "lam_out"), (lam_in, "lam_in")):
+            self._check_state(t, what)
+        self._check_dt(dt)
+        self._check_dx(dx)
         _ok(mhd_bunch_adjoint(self._h, _ptr(U_in), _ptr(lam_out), _ptr(lam_in), _ptr(dt), _ptr(dx),
                               _stream(stream)), "mhd_bunch_adjoint", self._h)
 
@@ -289,8 +319,10 @@ class Bunch:
     def autotune(self, U_in, U_out, dt, dx, reps=3, stream=None):
         """Time every launch configuration on these buffers and keep the fastest; returns
         (chosen index, [mean ms per update of each configuration])."""
-        self._check_state(U_in)
-        self._check_state(U_out)
+        self._check_state(U_in, "U_in")
+        self._check_state(U_out, "U_out")
+        self._check_dt(dt)
+        self._check_dx(dx)
         n = int(mhd_bunch_tile_count(self._h))
         ms = (C.c_float * n)()
         best = C.c_int32()
@@ -302,8 +334,12 @@ class Bunch:
         """Capture nsteps ping-pong steps (U_a -> U_b -> U_a ...) in one HIP graph;
         dt_mode 0 = dt as given, 1 = per-patch own CFL step, 2 = global minimum;
         nbr = device neighbour table to fill guards before each step, or None (frozen)."""
-        self._check_state(U_a)
-        self._check_state(U_b)
+        self._check_state(U_a, "U_a")
+        self._check_state(U_b, "U_b")
+        self._check_dt(dt)
+        self._check_dx(dx)
+        if nbr is not None:
+            self._check_nbr(nbr)
         self._graph_refs = (U_a, U_b, dt, dx, nbr)   # keep the bound buffers alive
         _ok(mhd_bunch_graph_capture(self._h, int(nsteps), _ptr(U_a), _ptr(U_b), _ptr(dt), _ptr(dx),
                                     None if nbr is None else _ptr(nbr), int(dt_mode),

@@ -160,6 +160,35 @@ def test_graph_with_guard_exchange_and_global_dt_matches_eager_calls():
     assert B.check() == 0
 
 
+def test_binding_rejects_mismatched_tensors():
+    """The library sees plain pointers, so the binding checks every buffer: a wrong element
+    type, count, layout or device raises before anything is launched."""
+    import torch
+    L, U, dx, gam = _ragged()
+    B = make_bunch(L, gam)
+    Ua, Ub = dev(U), dev(np.zeros_like(U))
+    dt = torch.full((L.P,), 1e-4, dtype=torch.float64, device="cuda")
+    dxd = dev(dx)
+    nb = torch.zeros((L.P, 27), dtype=torch.int32, device="cuda")
+    bad = [
+        lambda: B.update(Ua, Ub, dt.float(), dxd),                     # dt in float32
+        lambda: B.update(Ua, Ub, dt[:-1], dxd),                        # dt too short
+        lambda: B.update(Ua, Ub, dt, dxd.t()),                         # dx not contiguous
+        lambda: B.update(Ua.float(), Ub, dt, dxd),                     # state of the wrong type
+        lambda: B.update(Ua[:-1], Ub[:-1], dt, dxd),                   # state too short
+        lambda: B.update(Ua.cpu(), Ub, dt, dxd),                       # host tensor
+        lambda: B.cfl(Ua, dxd[:-1], dt),
+        lambda: B.fill_guards(Ua, nb.long()),                          # int64 neighbour table
+        lambda: B.graph_capture(2, Ua, Ub, dt, dxd, nbr=nb[:-1]),
+    ]
+    for k, call in enumerate(bad):
+        with pytest.raises(ValueError):
+            call()
+    torch.cuda.synchronize()
+    B.update(Ua, Ub, dt, dxd)                                          # the handle still works
+    assert B.check() == 0
+
+
 def test_graph_capture_rejects_bad_arguments():
     import torch
 
