@@ -116,7 +116,8 @@ mhd_status mhd_bunch_cfl(mhd_bunch* h, const void* U_dev, const double* dx_dev,
 
 /* One update of every patch: U_out owned cells and faces <- U_in advanced by dt[p].
  * U_in guards must be filled; U_out guards are not written.  U_in and U_out must not
- * overlap. */
+ * overlap.  A patch with dt[p] == 0 (at rest in a local-time-stepping run) is copied
+ * without computing anything (its guards are not read and its state is not checked). */
 mhd_status mhd_bunch_update(mhd_bunch* h, const void* U_in, void* U_out, const double* dt_dev,
                             const double* dx_dev, hipStream_t stream);
 

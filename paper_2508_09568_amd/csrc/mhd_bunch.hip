@@ -73,9 +73,11 @@ template <typename T>
 __global__ __launch_bounds__(BLK) void k_prim(const PatchDev* __restrict__ pt,
                                               const BoxBlock* __restrict__ blk,
                                               const T* __restrict__ U, T* __restrict__ S,
-                                              Consts<T> c, int g, int* status, int nb, int remap) {
+                                              const double* __restrict__ zdt, Consts<T> c, int g,
+                                              int* status, int nb, int remap) {
   for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
     const BoxBlock b = blk[logical_block(vb, nb, remap)];
+    if (zdt && zdt[b.patch] == 0.0) continue;
     const PatchDev& P = pt[b.patch];
     int i, j, k;
     if (!decode(P, BOX_PRIM, g, b.first, i, j, k)) continue;
@@ -86,10 +88,12 @@ __global__ __launch_bounds__(BLK) void k_prim(const PatchDev* __restrict__ pt,
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_en(const PatchDev* __restrict__ pt,
                                             const BoxBlock* __restrict__ blk,
-                                            const T* __restrict__ U, T* __restrict__ S, int g,
-                                            int nb, int remap) {
+                                            const T* __restrict__ U, T* __restrict__ S,
+                                            const double* __restrict__ zdt, int g, int nb,
+                                            int remap) {
   for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
     const BoxBlock b = blk[logical_block(vb, nb, remap)];
+    if (zdt && zdt[b.patch] == 0.0) continue;
     const PatchDev& P = pt[b.patch];
     int i, j, k;
     if (!decode(P, BOX_EN, g, b.first, i, j, k)) continue;
@@ -102,10 +106,12 @@ __global__ __launch_bounds__(BLK) void k_pred(const PatchDev* __restrict__ pt,
                                               const BoxBlock* __restrict__ blk,
                                               const T* __restrict__ U, T* __restrict__ S,
                                               const double* __restrict__ dt,
-                                              const double* __restrict__ dx, Consts<T> c, int g,
+                                              const double* __restrict__ dx,
+                                              const double* __restrict__ zdt, Consts<T> c, int g,
                                               int nb, int remap) {
   for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
     const BoxBlock b = blk[logical_block(vb, nb, remap)];
+    if (zdt && zdt[b.patch] == 0.0) continue;
     const PatchDev& P = pt[b.patch];
     int i, j, k;
     if (!decode(P, BOX_PRED, g, b.first, i, j, k)) continue;
@@ -138,6 +144,10 @@ __attribute__((amdgpu_waves_per_eu(SolveWaves<T, TX, TY, TZ, FORM>::value))) voi
   for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
     const TileDev tl = tiles[logical_block(vb, ntile, remap)];
     const PatchDev& P = pt[tl.patch];
+    if (dt[tl.patch] == 0.0) {  // a patch at rest this step: its owned values are copied
+      copy_tile<TX, TY, TZ>(ex, P, g, tl, Uin, Uout);
+      continue;
+    }
     solve_tile<T, TX, TY, TZ, FORM>(ex, lds, P, g, tl, Uin, Uout, S, dt[tl.patch],
                                     dx + 3 * tl.patch, c);
     ex.sync();  // the next tile reuses the shared memory
@@ -165,6 +175,7 @@ __attribute__((amdgpu_waves_per_eu(PredWaves<T, PX, PY, PZ>::value))) void k_pre
   int bad = 0;
   for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
     const TileDev tl = tiles[logical_block(vb, ntile, remap)];
+    if (dt[tl.patch] == 0.0) continue;  // patch at rest: no predictor values needed
     const PatchDev& P = pt[tl.patch];
     bad |= predict_tile<T, PX, PY, PZ>(ex, lds, P, g, tl, U, W, dt[tl.patch], dx + 3 * tl.patch, c);
     ex.sync();  // the next tile reuses the shared memory
@@ -178,10 +189,12 @@ template <typename T, int TX, int TY, int TZ>
 __global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS)) __attribute__((amdgpu_waves_per_eu(3)))
 void k_edges(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, T* __restrict__ S,
-    const double* __restrict__ dx, Consts<T> c, int g, int ntile, int remap) {
+    const double* __restrict__ dt, const double* __restrict__ dx, Consts<T> c, int g, int ntile,
+    int remap) {
   DevX ex;
   for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
     const TileDev tl = tiles[logical_block(vb, ntile, remap)];
+    if (dt[tl.patch] == 0.0) continue;  // patch at rest: no EMFs needed
     const PatchDev& P = pt[tl.patch];
     solve_tile<T, TX, TY, TZ, 3>(ex, (T*)nullptr, P, g, tl, (const T*)S, S, S, 1.0, dx + 3 * tl.patch,
                                  c);
@@ -577,8 +590,8 @@ void solve_launch(mhd_bunch* h, int nt, const TileDev* tl, const T* Uin, T* Uout
 }
 
 template <typename T, int X, int Y, int Z>
-void edges_launch(mhd_bunch* h, int nt, const TileDev* tl, T* S, const double* dx,
-                  const Consts<T>& c, hipStream_t s) {
+void edges_launch(mhd_bunch* h, int nt, const TileDev* tl, T* S, const double* dt,
+                  const double* dx, const Consts<T>& c, hipStream_t s) {
   int grid = nt;
   if (h->mode == 2) {
     int occ = 0;
@@ -589,7 +602,7 @@ void edges_launch(mhd_bunch* h, int nt, const TileDev* tl, T* S, const double* d
     grid = h->persistent_grid(nt, occ);
   }
   hipLaunchKernelGGL((k_edges<T, X, Y, Z>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0, s,
-                     h->d_pt(), tl, S, dx, c, h->g, nt, h->mode >= 1);
+                     h->d_pt(), tl, S, dt, dx, c, h->g, nt, h->mode >= 1);
 }
 
 // edges = true: the owned-edge pass of solver form 2; else the solver tiles
@@ -604,7 +617,7 @@ void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uou
 #define MHD_TRY(X, Y, Z)                                                                      \
   if (tc.x == X && tc.y == Y && tc.z == Z) {                                                  \
     if (edges)                                                                                \
-      edges_launch<T, X, Y, Z>(h, nt, tl, S, dx, c, s);                                       \
+      edges_launch<T, X, Y, Z>(h, nt, tl, S, dt, dx, c, s);                                       \
     else if (h->split == 2)                                                                   \
       solve_launch<T, X, Y, Z, 2>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                    \
     else if (h->split == 1)                                                                   \
@@ -661,22 +674,23 @@ mhd_status launch_update(mhd_bunch* h, const T* Uin, T* Uout, const double* dt, 
       const int nb = ch.nblk[BOX_PRIM];
       t0 = h->tic(s);
       hipLaunchKernelGGL(k_prim<T>, dim3(h->stage_grid(nb)), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_PRIM) + ch.blk0[BOX_PRIM], Uin, S, c, h->g, h->d_status(),
-                         nb, rm);
+                         h->d_blk(BOX_PRIM) + ch.blk0[BOX_PRIM], Uin, S, dt, c, h->g,
+                         h->d_status(), nb, rm);
       h->toc(s, MHD_KERNEL_PRIM, t0);
     }
     if (!h->fused && ch.nblk[BOX_EN]) {
       const int nb = ch.nblk[BOX_EN];
       t0 = h->tic(s);
       hipLaunchKernelGGL(k_en<T>, dim3(h->stage_grid(nb)), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_EN) + ch.blk0[BOX_EN], Uin, S, h->g, nb, rm);
+                         h->d_blk(BOX_EN) + ch.blk0[BOX_EN], Uin, S, dt, h->g, nb, rm);
       h->toc(s, MHD_KERNEL_EDGE_EMF_N, t0);
     }
     if (!h->fused && ch.nblk[BOX_PRED]) {
       const int nb = ch.nblk[BOX_PRED];
       t0 = h->tic(s);
       hipLaunchKernelGGL(k_pred<T>, dim3(h->stage_grid(nb)), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], Uin, S, dt, dx, c, h->g, nb, rm);
+                         h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], Uin, S, dt, dx, dt, c, h->g, nb,
+                         rm);
       h->toc(s, MHD_KERNEL_PREDICT, t0);
     }
     if (h->split == 2 && ch.ntile[h->shape]) {
@@ -770,15 +784,16 @@ mhd_status launch_adjoint(mhd_bunch* h, const T* U, const T* lam, T* lam_in, con
     // forward intermediates of this update (primitives, EMFs at t^n, predictor data)
     if (ch.nblk[BOX_PRIM])
       hipLaunchKernelGGL(k_prim<T>, dim3(ch.nblk[BOX_PRIM]), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_PRIM) + ch.blk0[BOX_PRIM], U, S, c, h->g, h->d_status(),
-                         ch.nblk[BOX_PRIM], 0);
+                         h->d_blk(BOX_PRIM) + ch.blk0[BOX_PRIM], U, S, (const double*)nullptr, c,
+                         h->g, h->d_status(), ch.nblk[BOX_PRIM], 0);
     if (ch.nblk[BOX_EN])
       hipLaunchKernelGGL(k_en<T>, dim3(ch.nblk[BOX_EN]), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_EN) + ch.blk0[BOX_EN], U, S, h->g, ch.nblk[BOX_EN], 0);
+                         h->d_blk(BOX_EN) + ch.blk0[BOX_EN], U, S, (const double*)nullptr, h->g,
+                         ch.nblk[BOX_EN], 0);
     if (ch.nblk[BOX_PRED])
       hipLaunchKernelGGL(k_pred<T>, dim3(ch.nblk[BOX_PRED]), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], U, S, dt, dx, c, h->g,
-                         ch.nblk[BOX_PRED], 0);
+                         h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], U, S, dt, dx,
+                         (const double*)nullptr, c, h->g, ch.nblk[BOX_PRED], 0);
     // reverse sweep: predictor data, EMFs at t^n, primitives, padded input state
     if (ch.nblk[BOX_PRED])
       hipLaunchKernelGGL(k_adj_w<T>, dim3(ch.nblk[BOX_PRED], NW), dim3(BLK), 0, s, h->d_pt(),

@@ -1001,6 +1001,24 @@ struct TileShape {
   static_assert(THREADS % 64 == 0, "solver work-groups are whole wavefronts");
 };
 
+// A tile of a patch whose time step is zero (at rest in a local-time-stepping run): the update
+// is the identity, so its cells' 8 values (cell fields and owned lower faces) are copied.
+template <int TX, int TY, int TZ, typename T, class X>
+__host__ __device__ __forceinline__ void copy_tile(X& ex, const PatchDev& P, int g,
+                                                   const TileDev& tl, const T* Uin, T* Uout) {
+  constexpr int ax = TX > 1, ay = TY > 1, az = TZ > 1;
+  const int tx = ax ? (P.n[0] - tl.x0 < TX ? P.n[0] - tl.x0 : TX) : 1;
+  const int ty = ay ? (P.n[1] - tl.y0 < TY ? P.n[1] - tl.y0 : TY) : 1;
+  const int tz = az ? (P.n[2] - tl.z0 < TZ ? P.n[2] - tl.z0 : TZ) : 1;
+  const int i0 = ax ? g + tl.x0 : 0, j0 = ay ? g + tl.y0 : 0, k0 = az ? g + tl.z0 : 0;
+  const T* u = Uin + P.ubase;
+  T* uo = Uout + P.ubase;
+  for (int it = ex.tid(); it < tx * ty * tz; it += ex.nthr()) {
+    const int64_t cell = cell_of(P, i0 + it % tx, j0 + (it / tx) % ty, k0 + it / (tx * ty));
+    for (int m = 0; m < 8; ++m) uo[m * P.Nc + cell] = u[m * P.Nc + cell];
+  }
+}
+
 // FORM 0: face fluxes and edge EMFs of the tile in shared memory together, then the update;
 // FORM 1: two phases (faces and hydro update, then edges and field update) sharing the
 // shared memory; FORM 2: faces only, the half-step edge EMFs having been computed once per

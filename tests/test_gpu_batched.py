@@ -38,6 +38,11 @@ def test_every_launch_configuration_gives_identical_bits(case):
     cfgs = B.tile_configs()
     assert len(cfgs) >= 2 and B.tile() == 0
     Ui, dtd, dxd = dev(U), dev(dt), dev(dx)
+    # every other patch at rest (dt = 0): copied, while the others match the full update
+    dtm = dt.copy()
+    dtm[::2] = 0.0
+    dtmd = dev(dtm)
+    expect = None
     outs = []
     modes = B.predictor_modes()
     assert len(modes) >= 2 and modes[0] == (0, 0, 0)
@@ -55,6 +60,17 @@ def test_every_launch_configuration_gives_identical_bits(case):
                 outs.append(host(Uo))
                 log(f"    predictor {fused} split {split} config {i} {cfg}: max|diff| vs first = "
                     f"{np.abs(outs[-1] - outs[0]).max():.3e}")
+                if expect is None:
+                    expect = outs[0].copy()
+                    for p in range(0, L.P, 2):
+                        L.interior(expect, p)[...] = L.interior(U, p)
+                Um = dev(np.zeros_like(U))
+                B.update(Ui, Um, dtmd, dxd)
+                assert B.check() == 0
+                got = host(Um)
+                for p in range(L.P):
+                    assert np.array_equal(L.interior(got, p), L.interior(expect, p)), \
+                        (fused, split, i, p)
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     err = rel_err_fields(L, outs[0], ref)
