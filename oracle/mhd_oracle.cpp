@@ -16,8 +16,9 @@
  *   TrcT   -- double or x87 extended precision, plus a hash of every branch outcome
  *             (the branch signature; extended precision serves finite differences).
  *
- * Readings of points the paper leaves open (limiter, predictor, EMF solver, CFL rule,
- * floors, guard width) are listed in the design doc; each function cites what it follows.
+ * Where the paper leaves a point open (limiter, predictor, EMF solver, CFL rule, floors,
+ * guard width), the function that needs it states the reading it takes; each function
+ * cites what it follows.
  */
 #include "mhd_oracle.h"
 
