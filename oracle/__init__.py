@@ -81,6 +81,7 @@ def lib():
         L.mhd_oracle_step_ext_many.argtypes = [C.c_int32, ip, C.c_int32, C.c_void_p, C.c_void_p,
                                                dp, dp, P(_Params), up]
         L.mhd_oracle_fill_guards_ext.argtypes = [C.c_int32, ip, C.c_int32, C.c_void_p, ip]
+        L.mhd_oracle_fill_guards_at.argtypes = [C.c_int32, ip, C.c_int32, dp, dp, dp, dp, ip, ip]
         L.mhd_oracle_count_ops.argtypes = [ip, C.c_int32, dp, C.c_double, dp, P(_Params), lp]
         L.mhd_oracle_hlld.argtypes = [dp, dp, P(_Params), dp, ip]
         L.mhd_oracle_cfast.argtypes = [C.c_double] * 6
@@ -206,6 +207,81 @@ def fill_guards(U, dims, g, nbr):
     if rc != 0:
         raise ValueError("mhd_oracle_fill_guards: inconsistent neighbour table")
     return U
+
+
+def fill_guards_at(U, U_prev, t, t_prev, dims, g, nbr, mask=None):
+    """In-place guard fill of U at each patch's own time t[p]: the owner's value linearly
+    interpolated between its slices (t_prev, U_prev) and (t, U) (local time stepping)."""
+    assert U.dtype == np.float64 and U.flags.c_contiguous
+    U_prev = _f64(U_prev)
+    dims = _i32(dims).reshape(-1, 3)
+    P = dims.shape[0]
+    nbr = _i32(nbr).reshape(-1, 27)
+    t, t_prev = _f64(t), _f64(t_prev)
+    assert t.shape == (P,) and t_prev.shape == (P,) and U_prev.shape == U.shape
+    m = None if mask is None else _i32(np.asarray(mask).astype(np.int32))
+    rc = lib().mhd_oracle_fill_guards_at(P, _i(dims), g, _d(U), _d(U_prev), _d(t), _d(t_prev),
+                                         _i(nbr), None if m is None else _i(m))
+    if rc != 0:
+        raise ValueError("mhd_oracle_fill_guards_at: invalid argument or neighbour table")
+    return U
+
+
+def lts_ready(t, t_end, nbr):
+    """Patches that may advance: below t_end, and no neighbour (any of the 26 directions)
+    behind them, so every guard value is an interpolation within the owner's two slices."""
+    t = np.asarray(t, dtype=np.float64)
+    nbr = np.asarray(nbr).reshape(-1, 27)
+    ready = t < t_end
+    for p in range(t.shape[0]):
+        for q in nbr[p]:
+            if q >= 0 and q != p and t[q] < t[p]:
+                ready[p] = False
+    return ready
+
+
+def lts_run(U, dims, g, dx, nbr, prm: Params, t_end, dt_fixed=None, max_steps=100000):
+    """Local time stepping to t_end (§2.2 "DISPATCH": each patch advances with its own time
+    step; guard zones interpolated in time from the neighbours' slices).  A step: the ready
+    patches (lts_ready) fill their guards at their own time (fill_guards_at), take their own
+    CFL step (or dt_fixed[p]) clipped to t_end and advance; the others stay.  The previous
+    slice of an advanced patch is its state before the step.  Returns (U, t, steps per patch,
+    number of steps)."""
+    U = _f64(U).copy()
+    dims = _i32(dims).reshape(-1, 3)
+    P = dims.shape[0]
+    base = np.zeros(P + 1, dtype=np.int64)
+    for p in range(P):
+        base[p + 1] = base[p] + patch_elems_of(dims[p], g)
+    Uprev = U.copy()
+    t = np.zeros(P)
+    tp = np.zeros(P)
+    count = np.zeros(P, dtype=np.int64)
+    nsteps = 0
+    while np.any(t < t_end):
+        if nsteps >= max_steps:
+            raise RuntimeError("lts_run: step limit reached")
+        ready = lts_ready(t, t_end, nbr)
+        fill_guards_at(U, Uprev, t, tp, dims, g, nbr, mask=ready)
+        dt = np.asarray(dt_fixed, dtype=np.float64).copy() if dt_fixed is not None else \
+            cfl_many(U, dims, g, dx, prm)
+        dt = np.where(ready, np.minimum(dt, t_end - t), 0.0)
+        Un = step_many(U, dims, g, dt, dx, prm)
+        for p in np.nonzero(ready)[0]:
+            Uprev[base[p]:base[p + 1]] = U[base[p]:base[p + 1]]
+        tp = np.where(ready, t, tp)
+        t = t + dt
+        count += ready
+        U = Un
+        nsteps += 1
+    return U, t, count, nsteps
+
+
+def patch_elems_of(n, g):
+    e = 8
+    for d in range(3):
+        e *= int(n[d]) + 2 * g if n[d] > 1 else 1
+    return e
 
 
 def jvp_many(U, dU, dims, g, dt, dx, prm: Params):

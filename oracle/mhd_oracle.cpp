@@ -659,17 +659,20 @@ long patch_elems(const int32_t n[3], int g) {
 
 /* ------------------------------------------------------------------ C interface */
 
-template <class E>
-int fill_guards_t(int32_t npatch, const int32_t* dims, int32_t g, E* U, const int32_t* nbr) {
-  if (npatch < 0 || !U || !nbr) return -1;
+/* Every guard cell of every patch with its owner (the framework's guard exchange, §2.2):
+ * f(p, cd, src, cs, Nc_p, Nc_src, base_p, base_src) for destination cell cd of patch p and
+ * source cell cs of patch src.  A direction whose face neighbour is the domain boundary
+ * takes the zero-gradient copy of the nearest owned cell. */
+template <class F>
+int for_each_guard(int32_t npatch, const int32_t* dims, int32_t g, const int32_t* nbr, F f) {
+  if (npatch < 0 || !nbr) return -1;
   std::vector<Geom> Gs(npatch);
   std::vector<long> base(npatch + 1, 0);
   for (int p = 0; p < npatch; ++p) {
     if (!Gs[p].init(dims + 3 * p, g)) return -1;
     base[p + 1] = base[p] + 8 * Gs[p].Nc;
   }
-  int bad = 0;
-  for (int p = 0; p < npatch && !bad; ++p) {
+  for (int p = 0; p < npatch; ++p) {
     const Geom& G = Gs[p];
     for (int k = 0; k < G.N[2]; ++k)
       for (int j = 0; j < G.N[1]; ++j)
@@ -684,7 +687,6 @@ int fill_guards_t(int32_t npatch, const int32_t* dims, int32_t g, E* U, const in
             if (o[d]) guard = true;
           }
           if (!guard) continue;
-          // directions whose face neighbour is the domain boundary: zero-gradient copy
           for (int d = 0; d < 3; ++d) {
             if (!o[d]) continue;
             int fo[3] = {0, 0, 0};
@@ -696,16 +698,25 @@ int fill_guards_t(int32_t npatch, const int32_t* dims, int32_t g, E* U, const in
           }
           int src = p;
           if (o[0] || o[1] || o[2]) src = nbr[27 * p + (o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1)];
-          if (src < 0 || src >= npatch) { bad = 1; break; }
+          if (src < 0 || src >= npatch) return -1;
           const Geom& H = Gs[src];
-          if (H.n[0] != G.n[0] || H.n[1] != G.n[1] || H.n[2] != G.n[2]) { bad = 1; break; }
+          if (H.n[0] != G.n[0] || H.n[1] != G.n[1] || H.n[2] != G.n[2]) return -1;
           const long cs = (idx[0] - o[0] * G.n[0]) + H.st[1] * (idx[1] - o[1] * G.n[1]) +
                           H.st[2] * (idx[2] - o[2] * G.n[2]);
           const long cd = (long)i + G.st[1] * j + G.st[2] * k;
-          for (int m = 0; m < 8; ++m) U[base[p] + m * G.Nc + cd] = U[base[src] + m * H.Nc + cs];
+          f(p, cd, src, cs, G.Nc, H.Nc, base[p], base[src]);
         }
   }
-  return bad ? -1 : 0;
+  return 0;
+}
+
+template <class E>
+int fill_guards_t(int32_t npatch, const int32_t* dims, int32_t g, E* U, const int32_t* nbr) {
+  if (!U) return -1;
+  return for_each_guard(npatch, dims, g, nbr,
+                        [&](int, long cd, int, long cs, long Nc, long Ns, long bp, long bs) {
+                          for (int m = 0; m < 8; ++m) U[bp + m * Nc + cd] = U[bs + m * Ns + cs];
+                        });
 }
 
 /* one update in arithmetic R with the branch signature (sig may be NULL) */
@@ -810,6 +821,28 @@ int mhd_oracle_fill_guards(int32_t npatch, const int32_t* dims, int32_t g, doubl
 int mhd_oracle_fill_guards_ext(int32_t npatch, const int32_t* dims, int32_t g, long double* U,
                                const int32_t* nbr) {
   return fill_guards_t(npatch, dims, g, U, nbr);
+}
+
+/* Guard fill at each patch's own time (local time stepping: §2.2 "DISPATCH", patches carry
+ * several time slices; §3.1 "DISPATCH Validation", guard zones interpolated between
+ * asynchronous patch times).  A guard cell of patch p whose owner is q receives q's value
+ * at time t[p], interpolated linearly between q's slices (t_prev[q], U_prev) and (t[q], U):
+ * (1 - th) U_prev + th U with th = (t[p] - t_prev[q]) / (t[q] - t_prev[q]); q's current
+ * value when t[q] == t_prev[q].  Patches with mask[p] == 0 are left alone (mask NULL: all). */
+int mhd_oracle_fill_guards_at(int32_t npatch, const int32_t* dims, int32_t g, double* U,
+                              const double* U_prev, const double* t, const double* t_prev,
+                              const int32_t* nbr, const int32_t* mask) {
+  if (!U || !U_prev || !t || !t_prev) return -1;
+  return for_each_guard(
+      npatch, dims, g, nbr, [&](int p, long cd, int q, long cs, long Nc, long Ns, long bp, long bs) {
+        if (mask && !mask[p]) return;
+        const bool two = t[q] > t_prev[q];
+        const double th = two ? (t[p] - t_prev[q]) / (t[q] - t_prev[q]) : 1.0;
+        for (int m = 0; m < 8; ++m) {
+          const double a = U_prev[bs + m * Ns + cs], b = U[bs + m * Ns + cs];
+          U[bp + m * Nc + cd] = two ? (1.0 - th) * a + th * b : b;
+        }
+      });
 }
 
 int mhd_oracle_step_jvp(const int32_t n[3], int32_t g, const double* U_in, const double* dU_in,

@@ -90,6 +90,13 @@ int mhd_oracle_step_ext_many(int32_t npatch, const int32_t* dims, int32_t g,
 int mhd_oracle_fill_guards_ext(int32_t npatch, const int32_t* dims, int32_t g, long double* U,
                                const int32_t* nbr);
 
+/* Guard fill at each patch's own time t[p] from two time slices of the owners: the owner q's
+ * value linearly interpolated between (t_prev[q], U_prev) and (t[q], U); its current value
+ * when t[q] == t_prev[q].  Patches with mask[p] == 0 are skipped (mask NULL: all). */
+int mhd_oracle_fill_guards_at(int32_t npatch, const int32_t* dims, int32_t g, double* U,
+                              const double* U_prev, const double* t, const double* t_prev,
+                              const int32_t* nbr, const int32_t* mask);
+
 /* Arithmetic performed by one patch update, counted by class:
  * counts[0] add/sub, [1] mul, [2] div, [3] sqrt, [4] compare/min/max/abs. */
 int mhd_oracle_count_ops(const int32_t n[3], int32_t g, const double* U_in, double dt,
