@@ -306,6 +306,73 @@ def run_batched(steps, steps_per_patch):
     }
 
 
+def run_lts(w, tile, t_mult):
+    """Local time stepping on the benchmark workload (FP64, the tuned launch configuration) to
+    t_end = t_mult x the largest power of two not above the smallest patch CFL step, against
+    global stepping (guard exchange + global CFL + update) to the same time.  Wall time
+    includes the host reading the times."""
+    import numpy as np
+    import torch
+
+    from paper_2508_09568_amd import lts
+    from paper_2508_09568_amd.binding import Bunch
+
+    L = w.layout
+    B = Bunch(L.dims, g=L.g, precision=8, gamma=w.gamma, cfl=w.cfl)
+    B.set_tile(B.tile_configs().index(tuple(tile["chosen"])))
+    B.set_predictor(tile["fused_predictor"])
+    B.set_solver_split(tile["solver_split"])
+    U = w.U.to(dtype=torch.float64, copy=True)
+    nbr = torch.as_tensor(w.nbr.astype(np.int32)).cuda()
+    dx = torch.as_tensor(w.dx).cuda()
+    dt = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    B.fill_guards(U, nbr)
+    B.cfl(U, dx, dt)
+    own = dt.cpu().numpy()
+    # time levels use a power-of-two quantum (exact time sums); t_end is a multiple of it
+    quantum = 2.0 ** np.floor(np.log2(float(own.min())))
+    t_end = t_mult * quantum
+    cells = int(np.prod(L.dims[0]))
+    # global stepping
+    Ua, Ub = U.clone(), torch.empty_like(U)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t, nglob = 0.0, 0
+    while t < t_end:
+        B.fill_guards(Ua, nbr)
+        B.cfl(Ua, dx, dt, global_min=True)
+        d = min(float(dt[0].item()), t_end - t)
+        dt.fill_(d)
+        B.update(Ua, Ub, dt, dx)
+        Ua, Ub = Ub, Ua
+        t = t_end if d >= t_end - t else t + d
+        nglob += 1
+    torch.cuda.synchronize()
+    wall_g = time.perf_counter() - t0
+    del Ua, Ub
+    upd_g = nglob * L.P * cells
+    res = {"t_end": t_end, "patch_dt_max_over_min": float(own.max() / own.min()),
+           "global": {"steps": nglob, "cell_updates": upd_g, "ms": 1e3 * wall_g,
+                      "cell_updates_per_s": upd_g / wall_g}}
+    # local time stepping: each patch at its own CFL step; then with time levels (steps
+    # rounded down to a power-of-two quantum x 2^k)
+    for key, q in (("lts", 0.0), ("lts_levels", quantum)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, tl, nl, cnt = lts.run(B, U, dx, nbr, t_end, dt_quantum=q, check_every=8)
+        torch.cuda.synchronize()
+        wall_l = time.perf_counter() - t0
+        if B.check() != 0:
+            raise RuntimeError("device status after the local-time-stepping run")
+        upd_l = int(cnt.sum().item()) * cells
+        res[key] = {"dt_quantum": q, "steps": nl,
+                    "updates_per_patch": [int(cnt.min().item()), int(cnt.max().item())],
+                    "cell_updates": upd_l, "ms": 1e3 * wall_l,
+                    "cell_updates_per_s": upd_l / wall_l,
+                    "work_ratio": upd_l / upd_g, "time_ratio": wall_l / wall_g}
+    return res
+
+
 def cpu_baseline(block):
     """The oracle's step on a corner block of block^3 patches of the same seeded turbulence
     (same cell size and patch shape), generated on the host; guards filled by the oracle
@@ -364,6 +431,10 @@ def main():
     ap.add_argument("--fp32-only", action="store_true",
                     help="skip the FP64 run (profiling of the FP32 kernels)")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--no-lts", action="store_true",
+                    help="skip the local-time-stepping run")
+    ap.add_argument("--lts-span", type=float, default=8.0,
+                    help="local-time-stepping run to this many smallest patch CFL steps")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run 5 plain device-to-device copies of this many bytes (HBM "
                          "counter calibration under rocprofv3 --pmc) and exit")
@@ -435,6 +506,17 @@ def main():
         log(f"[bench] batched vs per-bunch {batched['speedup_vs_per_bunch']:.2f}x, "
             f"vs per-patch {batched['speedup_vs_per_patch']:.2f}x")
 
+    lts_res = None
+    if not args.no_lts:
+        torch.cuda.empty_cache()
+        lts_res = run_lts(w, r64["tile"], args.lts_span)
+        for key in ("lts", "lts_levels"):
+            r = lts_res[key]
+            log(f"[bench] {key} to {lts_res['t_end']:.3e}: {r['steps']} steps, {r['ms']:.1f} "
+                f"ms, work {r['work_ratio']:.2f}x and time {r['time_ratio']:.2f}x of global "
+                f"stepping ({lts_res['global']['steps']} steps, "
+                f"{lts_res['global']['ms']:.1f} ms)")
+
     peak = PEAK_VALU_TFLOPS[8]
     out = {
         "metric": METRIC,
@@ -487,6 +569,7 @@ def main():
             "tile": r32["tile"],
         },
         "batched": batched,
+        "local_time_stepping": lts_res,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

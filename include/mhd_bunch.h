@@ -114,6 +114,32 @@ mhd_status mhd_bunch_fill_guards(mhd_bunch* h, void* U_dev, const int32_t* nbr_d
 mhd_status mhd_bunch_cfl(mhd_bunch* h, const void* U_dev, const double* dx_dev,
                          double* dt_dev, int32_t global, hipStream_t stream);
 
+/* One step of local time stepping (§2.2 "DISPATCH": every patch carries time slices and
+ * advances with its own time step; §3.1 "DISPATCH Validation": guard zones are interpolated
+ * between asynchronous patch times).  Device arrays: three state buffers (U_cur at times
+ * t[p], U_prev at t_prev[p], U_new), t[P], t_prev[P], dt[P] (written), dt_fixed[P] or NULL,
+ * dx[P][3], nbr[P][27] as for mhd_bunch_fill_guards.  On the stream, in order:
+ *  1. ready[p] = t[p] < t_end and no neighbour q (any of the 26 entries) has t[q] < t[p];
+ *  2. the guards of every ready patch p in U_cur are filled at its time t[p]: the owner q's
+ *     value (1 - th) U_prev + th U_cur with th = (t[p] - t_prev[q]) / (t[q] - t_prev[q]),
+ *     or its U_cur value when t[q] == t_prev[q] (weight and blend in double, then rounded);
+ *  3. dt[p] = ready ? min(d, t_end - t[p]) : 0 with d = dt_fixed ? dt_fixed[p] : the patch's
+ *     own CFL step, rounded down to dt_quantum x 2^k (k any integer) when dt_quantum > 0 (time
+ *     levels: patches then advance in lock-step groups, fewer steps per run; take a power
+ *     of two, so that the times of a level are exact sums);
+ *  4. U_new = mhd_bunch_update(U_cur, dt) (patches at rest are copied);
+ *  5. for every ready patch: U_prev <- U_cur (its whole padded block), t_prev[p] = t[p],
+ *     t[p] += dt[p] (exactly t_end when the step was clipped to it).
+ * The caller then swaps U_cur and U_new.  Start with t = t_prev (one slice per patch) and
+ * U_prev any buffer of the right size.  The run is over when every t[p] == t_end.  The three
+ * state buffers must not overlap, t, t_prev and dt must be distinct and dt_quantum must be
+ * finite and >= 0 (MHD_EINVAL); nothing is synchronised, so the step can be captured in a
+ * graph. */
+mhd_status mhd_bunch_lts_step(mhd_bunch* h, void* U_cur, void* U_new, void* U_prev, double* t_dev,
+                              double* t_prev_dev, double* dt_dev, const double* dt_fixed_dev,
+                              const double* dx_dev, const int32_t* nbr_dev, double t_end,
+                              double dt_quantum, hipStream_t stream);
+
 /* One update of every patch: U_out owned cells and faces <- U_in advanced by dt[p].
  * U_in guards must be filled; U_out guards are not written.  U_in and U_out must not
  * overlap.  A patch with dt[p] == 0 (at rest in a local-time-stepping run) is copied

@@ -240,12 +240,15 @@ def lts_ready(t, t_end, nbr):
     return ready
 
 
-def lts_run(U, dims, g, dx, nbr, prm: Params, t_end, dt_fixed=None, max_steps=100000):
+def lts_run(U, dims, g, dx, nbr, prm: Params, t_end, dt_fixed=None, dt_quantum=0.0,
+            max_steps=100000):
     """Local time stepping to t_end (§2.2 "DISPATCH": each patch advances with its own time
     step; guard zones interpolated in time from the neighbours' slices).  A step: the ready
     patches (lts_ready) fill their guards at their own time (fill_guards_at), take their own
-    CFL step (or dt_fixed[p]) clipped to t_end and advance; the others stay.  The previous
-    slice of an advanced patch is its state before the step.  Returns (U, t, steps per patch,
+    CFL step (or dt_fixed[p]; with dt_quantum > 0 rounded down to dt_quantum x 2^k, k an
+    integer: time levels) clipped to t_end and advance (a clipped step ends exactly at t_end);
+    the others stay.  The previous slice of an advanced patch is its state before the
+    step.  Returns (U, t, steps per patch,
     number of steps)."""
     U = _f64(U).copy()
     dims = _i32(dims).reshape(-1, 3)
@@ -265,12 +268,15 @@ def lts_run(U, dims, g, dx, nbr, prm: Params, t_end, dt_fixed=None, max_steps=10
         fill_guards_at(U, Uprev, t, tp, dims, g, nbr, mask=ready)
         dt = np.asarray(dt_fixed, dtype=np.float64).copy() if dt_fixed is not None else \
             cfl_many(U, dims, g, dx, prm)
+        if dt_quantum > 0:
+            _, e = np.frexp(dt / dt_quantum)               # dt / quantum in [2^(e-1), 2^e)
+            dt = np.ldexp(np.full(P, float(dt_quantum)), e - 1)
         dt = np.where(ready, np.minimum(dt, t_end - t), 0.0)
         Un = step_many(U, dims, g, dt, dx, prm)
         for p in np.nonzero(ready)[0]:
             Uprev[base[p]:base[p + 1]] = U[base[p]:base[p + 1]]
         tp = np.where(ready, t, tp)
-        t = t + dt
+        t = np.where(ready & (dt >= t_end - t), t_end, t + dt)   # the last step lands on t_end
         count += ready
         U = Un
         nsteps += 1

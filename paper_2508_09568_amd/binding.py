@@ -92,6 +92,8 @@ _SIGS = {
     "mhd_bunch_autotune": (C.c_int, [_h, _v, _v, _v, _v, C.c_int32, _st, _ip,
                                      C.POINTER(C.c_float)]),
     "mhd_bunch_graph_capture": (C.c_int, [_h, C.c_int32, _v, _v, _v, _v, _v, C.c_int32, _st]),
+    "mhd_bunch_lts_step": (C.c_int, [_h, _v, _v, _v, _v, _v, _v, _v, _v, _v, C.c_double,
+                                     C.c_double, _st]),
     "mhd_bunch_graph_launch": (C.c_int, [_h, _st]),
     "mhd_bunch_set_predictor": (C.c_int, [_h, C.c_int32]),
     "mhd_bunch_predictor": (C.c_int32, [_h]),
@@ -204,6 +206,10 @@ class Bunch:
     def _check_dt(self, dt):
         import torch
         self._check(dt, torch.float64, self.P, "dt")
+
+    def _check_dt_named(self, x, what):
+        import torch
+        self._check(x, torch.float64, self.P, what)
 
     def _check_dx(self, dx):
         import torch
@@ -344,6 +350,27 @@ class Bunch:
         _ok(mhd_bunch_graph_capture(self._h, int(nsteps), _ptr(U_a), _ptr(U_b), _ptr(dt), _ptr(dx),
                                     None if nbr is None else _ptr(nbr), int(dt_mode),
                                     _stream(stream)), "mhd_bunch_graph_capture", self._h)
+
+    def lts_step(self, U_cur, U_new, U_prev, t, t_prev, dt, dx, nbr, t_end, dt_fixed=None,
+                 dt_quantum=0.0, stream=None):
+        """One local time step (see include/mhd_bunch.h): ready patches fill their guards at
+        their own time from the owners' two slices and advance by their own CFL step (or
+        dt_fixed; rounded down to dt_quantum x 2^k if dt_quantum > 0) clipped to t_end; the
+        others stay.  t, t_prev and dt (written) are (P,) float64 device tensors.  The caller
+        swaps U_cur and U_new afterwards."""
+        for x, what in ((U_cur, "U_cur"), (U_new, "U_new"), (U_prev, "U_prev")):
+            self._check_state(x, what)
+        for x, what in ((t, "t"), (t_prev, "t_prev"), (dt, "dt")):
+            self._check_dt_named(x, what)
+        if dt_fixed is not None:
+            self._check_dt_named(dt_fixed, "dt_fixed")
+        self._check_dx(dx)
+        self._check_nbr(nbr)
+        _ok(mhd_bunch_lts_step(self._h, _ptr(U_cur), _ptr(U_new), _ptr(U_prev), _ptr(t),
+                               _ptr(t_prev), _ptr(dt), None if dt_fixed is None else _ptr(dt_fixed),
+                               _ptr(dx), _ptr(nbr), float(t_end), float(dt_quantum),
+                               _stream(stream)),
+            "mhd_bunch_lts_step", self._h)
 
     def graph_launch(self, stream=None):
         _ok(mhd_bunch_graph_launch(self._h, _stream(stream)), "mhd_bunch_graph_launch", self._h)

@@ -14,8 +14,10 @@
 //               the EMFs k_edges left) into shared memory, then the conservative +
 //               constrained-transport update.
 // Side kernels: k_cfl / k_cfl_final (per-patch time step, wavefront max-reduction + one
-// 64-bit atomic per work-group), k_guards (guard fill from a neighbour table), and the
-// k_adj_* reverse sweep of the adjoint, which re-runs the staged predictor kernels first.
+// 64-bit atomic per work-group), k_guards (guard fill from a neighbour table), the local
+// time stepping step (k_lts_ready, k_guards_at, k_lts_dt, k_lts_keep, k_lts_time around
+// the update), and the k_adj_* reverse sweep of the adjoint, which re-runs the staged
+// predictor kernels first.  Patches with dt = 0 are copied by the update, not computed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -261,6 +263,90 @@ __global__ __launch_bounds__(BLK) void k_guards(const PatchDev* __restrict__ pt,
   if (guard_item(pt, b.patch, g, i, j, k, U, nbr, np)) atomicOr(status, 2);
 }
 
+// ------------------------------------------------------- local time stepping kernels
+// A patch is ready when it is below t_end and none of its neighbours (26 directions) is
+// behind it: every guard value it needs then lies between an owner's two slices.
+__global__ __launch_bounds__(BLK) void k_lts_ready(const int32_t* __restrict__ nbr,
+                                                   const double* __restrict__ t, double t_end,
+                                                   int32_t* __restrict__ ready, int np) {
+  const int p = blockIdx.x * BLK + threadIdx.x;
+  if (p >= np) return;
+  const double tp = t[p];
+  int r = tp < t_end;
+  for (int o = 0; o < 27 && r; ++o) {
+    const int q = nbr[27 * p + o];
+    if (q >= 0 && q < np && q != p && t[q] < tp) r = 0;
+  }
+  ready[p] = r;
+}
+
+// guard cells of the ready patches at their own time
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_guards_at(const PatchDev* __restrict__ pt,
+                                                   const BoxBlock* __restrict__ blk, T* U,
+                                                   const T* __restrict__ Uprev,
+                                                   const double* __restrict__ t,
+                                                   const double* __restrict__ tprev,
+                                                   const int32_t* __restrict__ nbr,
+                                                   const int32_t* __restrict__ ready, int g,
+                                                   int np, int* status) {
+  const BoxBlock b = blk[blockIdx.x];
+  if (!ready[b.patch]) return;
+  const PatchDev& P = pt[b.patch];
+  const int q = b.first + (int)threadIdx.x;
+  if (q >= guard_count(P)) return;
+  int i, j, k;
+  guard_cell(P, g, q, i, j, k);
+  if (guard_item_at(pt, b.patch, g, i, j, k, U, Uprev, t, tprev, nbr, np)) atomicOr(status, 2);
+}
+
+// step of each patch: its own (or the given) step, rounded down to quantum x 2^k when a
+// quantum is given (time levels: exact powers of two, frexp is exact), clipped to t_end when
+// ready, else zero
+__global__ __launch_bounds__(BLK) void k_lts_dt(const int32_t* __restrict__ ready,
+                                                const double* __restrict__ t, double t_end,
+                                                double quantum, const double* src, double* dt,
+                                                int np) {
+  const int p = blockIdx.x * BLK + threadIdx.x;
+  if (p >= np) return;
+  double d = src[p];
+  if (quantum > 0.0) {
+    int e;
+    (void)frexp(d / quantum, &e);  // d / quantum in [2^(e-1), 2^e)
+    d = ldexp(quantum, e - 1);
+  }
+  const double rest = t_end - t[p];
+  dt[p] = ready[p] ? (d < rest ? d : rest) : 0.0;
+}
+
+// previous slice of every ready patch <- its state before the step (all padded cells)
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_lts_keep(const PatchDev* __restrict__ pt,
+                                                  const BoxBlock* __restrict__ blk,
+                                                  const T* __restrict__ U, T* __restrict__ Uprev,
+                                                  const int32_t* __restrict__ ready, int g) {
+  const BoxBlock b = blk[blockIdx.x];
+  if (!ready[b.patch]) return;
+  const PatchDev& P = pt[b.patch];
+  int x[3];
+  if (!decode(P, BOX_ALL, g, b.first, x[0], x[1], x[2])) return;
+  const int64_t cell = cell_of(P, x[0], x[1], x[2]);
+  for (int m = 0; m < 8; ++m) Uprev[P.ubase + m * P.Nc + cell] = U[P.ubase + m * P.Nc + cell];
+}
+
+// time of every ready patch advances by its step; a step clipped to t_end ends exactly there
+__global__ __launch_bounds__(BLK) void k_lts_time(const int32_t* __restrict__ ready,
+                                                  double* __restrict__ t,
+                                                  double* __restrict__ tprev,
+                                                  const double* __restrict__ dt, double t_end,
+                                                  int np) {
+  const int p = blockIdx.x * BLK + threadIdx.x;
+  if (p >= np || !ready[p]) return;
+  const double tp = t[p];
+  tprev[p] = tp;
+  t[p] = dt[p] >= t_end - tp ? t_end : tp + dt[p];
+}
+
 // ------------------------------------------------------------------- adjoint kernels
 // grid.x: block table of the item box, grid.y: component
 
@@ -459,6 +545,7 @@ struct mhd_bunch {
   std::vector<TileDev> ptiles[MAXPSHAPE];
   size_t o_ptiles[MAXPSHAPE] = {0};
   int64_t scratch_elems = 0;
+  size_t o_ready = 0;  // local time stepping: ready flag per patch (int32)
   size_t o_pt = 0, o_blk[NBOX] = {0}, o_tiles[MAXSHAPE] = {0}, o_smax = 0, o_status = 0,
          o_scratch = 0;
   // mhd_bunch_graph_capture: instantiated graph of a multi-step run
@@ -546,6 +633,7 @@ struct mhd_bunch {
   const TileDev* d_ptiles(int k) const { return (const TileDev*)(ws + o_ptiles[k]); }
   unsigned long long* d_smax() const { return (unsigned long long*)(ws + o_smax); }
   int* d_status() const { return (int*)(ws + o_status); }
+  int32_t* d_ready() const { return (int32_t*)(ws + o_ready); }
   void* d_scratch() const { return ws + o_scratch; }
 };
 
@@ -818,6 +906,38 @@ mhd_status launch_adjoint(mhd_bunch* h, const T* U, const T* lam, T* lam_in, con
   return h->hip_ok(hipGetLastError(), "launch adjoint kernels") ? MHD_OK : MHD_EDEVICE;
 }
 
+template <typename T>
+mhd_status launch_lts_step(mhd_bunch* h, T* Ucur, T* Unew, T* Uprev, double* t, double* tprev,
+                           double* dt, const double* dt_fixed, const double* dx,
+                           const int32_t* nbr, double t_end, double quantum, hipStream_t s) {
+  const int pg = (h->P + BLK - 1) / BLK;
+  int32_t* ready = h->d_ready();
+  hipLaunchKernelGGL(k_lts_ready, dim3(pg), dim3(BLK), 0, s, nbr, (const double*)t, t_end, ready,
+                     h->P);
+  const int ng = (int)h->blocks[BOX_GUARD].size();
+  if (ng) {
+    hipEvent_t t0 = h->tic(s);
+    hipLaunchKernelGGL(k_guards_at<T>, dim3(ng), dim3(BLK), 0, s, h->d_pt(), h->d_blk(BOX_GUARD),
+                       Ucur, (const T*)Uprev, (const double*)t, (const double*)tprev, nbr,
+                       (const int32_t*)ready, h->g, h->P, h->d_status());
+    h->toc(s, MHD_KERNEL_GUARDS, t0);
+  }
+  if (!dt_fixed) {
+    const mhd_status st = launch_cfl<T>(h, (const T*)Ucur, dx, dt, 0, s);
+    if (st != MHD_OK) return st;
+  }
+  hipLaunchKernelGGL(k_lts_dt, dim3(pg), dim3(BLK), 0, s, (const int32_t*)ready, (const double*)t,
+                     t_end, quantum, dt_fixed ? dt_fixed : (const double*)dt, dt, h->P);
+  const mhd_status st = launch_update<T>(h, (const T*)Ucur, Unew, dt, dx, s);
+  if (st != MHD_OK) return st;
+  const int na = (int)h->blocks[BOX_ALL].size();
+  hipLaunchKernelGGL(k_lts_keep<T>, dim3(na), dim3(BLK), 0, s, h->d_pt(), h->d_blk(BOX_ALL),
+                     (const T*)Ucur, Uprev, (const int32_t*)ready, h->g);
+  hipLaunchKernelGGL(k_lts_time, dim3(pg), dim3(BLK), 0, s, (const int32_t*)ready, t, tprev,
+                     (const double*)dt, t_end, h->P);
+  return h->hip_ok(hipGetLastError(), "launch local time step") ? MHD_OK : MHD_EDEVICE;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------ C ABI
@@ -1019,6 +1139,8 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
   o = align256(o + sizeof(unsigned long long) * h->P);
   h->o_status = o;
   o = align256(o + sizeof(unsigned long long));
+  h->o_ready = o;
+  o = align256(o + sizeof(int32_t) * h->P);
   h->o_scratch = o;
   o = align256(o + (size_t)h->scratch_elems * esz);
   h->ws_bytes = o;
@@ -1169,6 +1291,26 @@ mhd_status mhd_bunch_update(mhd_bunch* h, const void* Uin, void* Uout, const dou
   if (a < b + bytes && b < a + bytes) return MHD_EINVAL;
   return h->prec == 8 ? launch_update<double>(h, (const double*)Uin, (double*)Uout, dt, dx, s)
                       : launch_update<float>(h, (const float*)Uin, (float*)Uout, dt, dx, s);
+}
+
+mhd_status mhd_bunch_lts_step(mhd_bunch* h, void* U_cur, void* U_new, void* U_prev, double* t,
+                              double* t_prev, double* dt, const double* dt_fixed,
+                              const double* dx, const int32_t* nbr, double t_end,
+                              double dt_quantum, hipStream_t s) {
+  if (!h || !U_cur || !U_new || !U_prev || !t || !t_prev || !dt || !dx || !nbr) return MHD_EINVAL;
+  if (!(t_end == t_end) || t == t_prev || dt == t || dt == t_prev) return MHD_EINVAL;
+  if (!(dt_quantum >= 0.0) || dt_quantum > 1e300) return MHD_EINVAL;
+  if (!h->bound) return MHD_ESTATE;
+  const size_t bytes = (size_t)h->state_elems * h->prec;
+  const char* b[3] = {(const char*)U_cur, (const char*)U_new, (const char*)U_prev};
+  for (int x = 0; x < 3; ++x)
+    for (int y = x + 1; y < 3; ++y)
+      if (b[x] < b[y] + bytes && b[y] < b[x] + bytes) return MHD_EINVAL;
+  return h->prec == 8
+             ? launch_lts_step<double>(h, (double*)U_cur, (double*)U_new, (double*)U_prev, t,
+                                       t_prev, dt, dt_fixed, dx, nbr, t_end, dt_quantum, s)
+             : launch_lts_step<float>(h, (float*)U_cur, (float*)U_new, (float*)U_prev, t, t_prev,
+                                      dt, dt_fixed, dx, nbr, t_end, dt_quantum, s);
 }
 
 mhd_status mhd_bunch_check(mhd_bunch* h, hipStream_t s) {

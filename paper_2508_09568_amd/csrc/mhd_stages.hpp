@@ -661,6 +661,37 @@ __host__ __device__ __forceinline__ int guard_item(const PatchDev* PT, int p, in
   return 0;
 }
 
+// Local time stepping: patch p fills its guards at its own time t[p] from two time slices
+// of each owner q, (t_prev[q], U_prev) and (t[q], U).  The weight and the blend are taken in
+// double without contraction (the same two roundings for every value), then rounded to T;
+// an owner with a single slice (t[q] == t_prev[q]) gives its current value.
+__host__ __device__ inline double time_blend(double th, double a, double b) {
+#pragma clang fp contract(off)
+  return (1.0 - th) * a + th * b;
+}
+template <typename T>
+__host__ __device__ __forceinline__ int guard_item_at(const PatchDev* PT, int p, int g, int i, int j,
+                                                      int k, T* U, const T* Uprev, const double* t,
+                                                      const double* tprev, const int32_t* nbr,
+                                                      int npatch) {
+  int src;
+  int64_t cs;
+  const int r = guard_source(PT, p, g, i, j, k, nbr, npatch, src, cs);
+  if (r == 0) return 0;
+  if (r < 0) return 1;
+  const PatchDev& P = PT[p];
+  const PatchDev& Q = PT[src];
+  const int64_t cd = cell_of(P, i, j, k);
+  const bool two = t[src] > tprev[src];
+  const double th = two ? (t[p] - tprev[src]) / (t[src] - tprev[src]) : 1.0;
+  for (int m = 0; m < 8; ++m) {
+    const int64_t e = Q.ubase + m * Q.Nc + cs;
+    const double b = (double)U[e];
+    U[P.ubase + m * P.Nc + cd] = (T)(two ? time_blend(th, (double)Uprev[e], b) : b);
+  }
+  return 0;
+}
+
 // ================================================================ adjoint stages
 // The adjoint of one update at fixed dt is assembled stage by stage in reverse order.  Each
 // adjoint element is a gather over the forward items that read the corresponding input:

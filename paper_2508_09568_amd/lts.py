@@ -1,0 +1,33 @@
+"""Local time stepping over a bunch: every patch advances with its own time step and fills
+its guards at its own time from the neighbours' two time slices (the asynchronous patch
+updates of the paper's §2.2 "DISPATCH"; guard interpolation between patch times, §3.1).
+Each step is one `mhd_bunch_lts_step` call; the host only reads the patch times to stop."""
+from __future__ import annotations
+
+import torch
+
+
+def run(bunch, U, dx, nbr, t_end, dt_fixed=None, dt_quantum=0.0, check_every=16,
+        max_steps=1_000_000):
+    """Advance the state tensor U (guards filled or not) to t_end; dt_quantum > 0 rounds every
+    step down to dt_quantum x 2^k (time levels).  Returns (U at t_end, t (all t_end), number
+    of steps, updates per patch)."""
+    P = bunch.P
+    dev = U.device
+    Ua, Ub, Up = U.clone(), torch.empty_like(U), U.clone()
+    t = torch.zeros(P, dtype=torch.float64, device=dev)
+    tp = torch.zeros(P, dtype=torch.float64, device=dev)
+    dt = torch.zeros(P, dtype=torch.float64, device=dev)
+    count = torch.zeros(P, dtype=torch.int64, device=dev)
+    n = 0
+    while n < max_steps:
+        bunch.lts_step(Ua, Ub, Up, t, tp, dt, dx, nbr, t_end, dt_fixed=dt_fixed,
+                       dt_quantum=dt_quantum)
+        count += dt > 0
+        Ua, Ub = Ub, Ua
+        n += 1
+        if n % check_every == 0 and bool((t >= t_end).all()):
+            break
+    else:
+        raise RuntimeError("lts.run: step limit reached")
+    return Ua, t, n, count

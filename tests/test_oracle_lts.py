@@ -106,3 +106,27 @@ def test_cfl_driven_run_stays_close_to_synchronous_stepping(ora):
     num = sum(np.abs(L.interior(Ul, p) - L.interior(Us, p)).sum() for p in range(L.P))
     den = sum(np.abs(L.interior(Us, p)).sum() for p in range(L.P))
     assert num / den < 1e-3, num / den
+
+
+def test_time_levels_round_steps_to_powers_of_two_of_the_quantum(ora):
+    """dt_quantum > 0: every step is dt_quantum x 2^k, at most the patch's own step, so the
+    patches advance in lock-step groups (with a power-of-two quantum every time is an exact
+    sum); the run ends at t_end close to synchronous stepping."""
+    w, U = _ot(ora)
+    L = w.layout
+    prm = ora.Params(gamma=w.gamma)
+    own = ora.cfl_many(U, L.dims, L.g, w.dx, prm)
+    q = 2.0 ** np.floor(np.log2(0.7 * float(own.min())))   # a power of two: exact time sums
+    dtf = own * np.linspace(1.0, 3.0, L.P)              # spread the steps over a few levels
+    Ul, t, cnt, ns = ora.lts_run(U, L.dims, L.g, w.dx, w.nbr, prm, t_end=8 * q, dt_fixed=dtf,
+                                 dt_quantum=q)
+    _, e = np.frexp(dtf / q)
+    lev = np.ldexp(q, e - 1)
+    assert np.all(lev <= dtf) and np.all(2 * lev > dtf)
+    assert np.all(t == 8 * q)
+    assert np.array_equal(cnt, np.ceil(8 * q / lev).astype(np.int64))
+    assert ns == 8                                       # the finest level sets the step count
+    Us = ora.run(U, L.dims, L.g, w.dx, w.nbr, prm, nsteps=8, dt_fixed=q)
+    num = sum(np.abs(L.interior(Ul, p) - L.interior(Us, p)).sum() for p in range(L.P))
+    den = sum(np.abs(L.interior(Us, p)).sum() for p in range(L.P))
+    assert num / den < 1e-3, num / den
