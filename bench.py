@@ -39,17 +39,17 @@ def log(*a):
 # launch configuration ((tile x, y, z, mode), predictor mode, solver form); valid only for
 # the kernel sources it was measured on: reported as null once they change.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "a6c34c0a2a3e1b3dfd3934744a2404737df45b3cc05d371725bc41c9bf27ff5e",
+    "sources_sha256": "0a08603005cd32b129e08c4b6e1d4e0178b7223ce0291cae64a10ed3734fae37",
     "bytes_per_update": {
-        "[32, 4, 2, 1]/1/0": 198.69e9,
-        "[32, 4, 4, 1]/1/0": 168.48e9,
-        "[32, 8, 2, 1]/1/0": 166.44e9,
-        "[32, 4, 2, 1]/1/1": 196.67e9,
-        "[32, 4, 4, 1]/1/1": 229.07e9,
-        "[32, 8, 2, 1]/1/1": 231.19e9,
-        "[32, 4, 2, 1]/1/2": 233.49e9,
-        "[32, 4, 4, 1]/1/2": 228.69e9,
-        "[32, 8, 2, 1]/1/2": 225.73e9,
+        "[32, 4, 2, 1]/1/0": 198.34e9,
+        "[32, 4, 4, 1]/1/0": 168.19e9,
+        "[32, 8, 2, 1]/1/0": 166.73e9,
+        "[32, 4, 2, 1]/1/1": 195.34e9,
+        "[32, 4, 4, 1]/1/1": 227.76e9,
+        "[32, 8, 2, 1]/1/1": 231.03e9,
+        "[32, 4, 2, 1]/1/2": 231.57e9,
+        "[32, 4, 4, 1]/1/2": 226.76e9,
+        "[32, 8, 2, 1]/1/2": 224.45e9,
     },
     "profile": "profiles/mhd_update_turbulence512_pmc.md",
 }
