@@ -204,8 +204,7 @@ class Bunch:
         self._check(U, self.dtype, self.state_elems, what)
 
     def _check_dt(self, dt):
-        import torch
-        self._check(dt, torch.float64, self.P, "dt")
+        self._check_dt_named(dt, "dt")
 
     def _check_dt_named(self, x, what):
         import torch
