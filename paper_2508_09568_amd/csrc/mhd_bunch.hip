@@ -207,8 +207,10 @@ template <typename T>
 __global__ __launch_bounds__(BLK) void k_cfl(const PatchDev* __restrict__ pt,
                                              const BoxBlock* __restrict__ blk,
                                              const T* __restrict__ U, const double* __restrict__ dx,
-                                             Consts<T> c, int g, unsigned long long* smax) {
+                                             const int32_t* __restrict__ mask, Consts<T> c, int g,
+                                             unsigned long long* smax) {
   const BoxBlock b = blk[blockIdx.x];
+  if (mask && !mask[b.patch]) return;  // whole work-group: patch not asked for (its dt: inf)
   const PatchDev& P = pt[b.patch];
   int i, j, k;
   double s = 0.0;
@@ -797,13 +799,13 @@ mhd_status launch_update(mhd_bunch* h, const T* Uin, T* Uout, const double* dt, 
 
 template <typename T>
 mhd_status launch_cfl(mhd_bunch* h, const T* U, const double* dx, double* dt, int global,
-                      hipStream_t s) {
+                      hipStream_t s, const int32_t* mask = nullptr) {
   const Consts<T> c = h->consts<T>();
   hipEvent_t t0 = h->tic(s);
   hipLaunchKernelGGL(k_zero_u64, dim3((h->P + 255) / 256), dim3(256), 0, s, h->d_smax(), h->P);
   const int nb = (int)h->blocks[BOX_INTERIOR].size();
-  hipLaunchKernelGGL(k_cfl<T>, dim3(nb), dim3(BLK), 0, s, h->d_pt(), h->d_blk(BOX_INTERIOR), U, dx, c,
-                     h->g, h->d_smax());
+  hipLaunchKernelGGL(k_cfl<T>, dim3(nb), dim3(BLK), 0, s, h->d_pt(), h->d_blk(BOX_INTERIOR), U, dx,
+                     mask, c, h->g, h->d_smax());
   hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(BLK), 0, s, h->P, (const unsigned long long*)h->d_smax(),
                      h->cfl, dt, global);
   h->toc(s, MHD_KERNEL_CFL, t0);
@@ -923,7 +925,7 @@ mhd_status launch_lts_step(mhd_bunch* h, T* Ucur, T* Unew, T* Uprev, double* t, 
     h->toc(s, MHD_KERNEL_GUARDS, t0);
   }
   if (!dt_fixed) {
-    const mhd_status st = launch_cfl<T>(h, (const T*)Ucur, dx, dt, 0, s);
+    const mhd_status st = launch_cfl<T>(h, (const T*)Ucur, dx, dt, 0, s, ready);
     if (st != MHD_OK) return st;
   }
   hipLaunchKernelGGL(k_lts_dt, dim3(pg), dim3(BLK), 0, s, (const int32_t*)ready, (const double*)t,
