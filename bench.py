@@ -39,17 +39,17 @@ def log(*a):
 # launch configuration ((tile x, y, z, mode), predictor mode, solver form); valid only for
 # the kernel sources it was measured on: reported as null once they change.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "6eaa83eef37546e145c99b2fa2f10063f6687cbe70c12cb8cee89ef7ef1248bf",
+    "sources_sha256": "ea2f59030dbca4daff7bf252a9540f87ce0b9e6627ef77318502c57f4e1037d9",
     "bytes_per_update": {
-        "[32, 4, 2, 1]/1/0": 198.34e9,
-        "[32, 4, 4, 1]/1/0": 168.19e9,
-        "[32, 8, 2, 1]/1/0": 166.73e9,
-        "[32, 4, 2, 1]/1/1": 195.34e9,
-        "[32, 4, 4, 1]/1/1": 227.76e9,
-        "[32, 8, 2, 1]/1/1": 231.03e9,
-        "[32, 4, 2, 1]/1/2": 231.57e9,
-        "[32, 4, 4, 1]/1/2": 226.76e9,
-        "[32, 8, 2, 1]/1/2": 224.45e9,
+        "[32, 4, 2, 1]/1/0": 198.36e9,
+        "[32, 4, 4, 1]/1/0": 168.05e9,
+        "[32, 8, 2, 1]/1/0": 166.40e9,
+        "[32, 4, 2, 1]/1/1": 196.19e9,
+        "[32, 4, 4, 1]/1/1": 228.51e9,
+        "[32, 8, 2, 1]/1/1": 231.84e9,
+        "[32, 4, 2, 1]/1/2": 232.57e9,
+        "[32, 4, 4, 1]/1/2": 227.51e9,
+        "[32, 8, 2, 1]/1/2": 225.89e9,
     },
     "profile": "profiles/mhd_update_turbulence512_pmc.md",
 }

@@ -127,11 +127,14 @@ mhd_status mhd_bunch_cfl(mhd_bunch* h, const void* U_dev, const double* dx_dev,
  *     own CFL step, rounded down to dt_quantum x 2^k (k any integer) when dt_quantum > 0 (time
  *     levels: patches then advance in lock-step groups, fewer steps per run; take a power
  *     of two, so that the times of a level are exact sums);
- *  4. U_new = mhd_bunch_update(U_cur, dt) (patches at rest are copied);
- *  5. for every ready patch: U_prev <- U_cur (its whole padded block), t_prev[p] = t[p],
- *     t[p] += dt[p] (exactly t_end when the step was clipped to it).
- * The caller then swaps U_cur and U_new.  Start with t = t_prev (one slice per patch) and
- * U_prev any buffer of the right size.  The run is over when every t[p] == t_end.  The three
+ *  4. the ready patches are updated from U_cur into U_new (scratch: patches at rest are
+ *     neither computed nor written);
+ *  5. for every ready patch: U_prev <- U_cur (its whole padded block), then U_cur's owned
+ *     cells and faces <- U_new's, t_prev[p] = t[p], t[p] += dt[p] (exactly t_end when the
+ *     step was clipped to it).
+ * On return U_cur holds every patch at its time t[p] (no buffers to swap).  Start with
+ * t = t_prev (one slice per patch) and U_prev any buffer of the right size.  The run is over
+ * when every t[p] == t_end.  The three
  * state buffers must not overlap, t, t_prev and dt must be distinct and dt_quantum must be
  * finite and >= 0 (MHD_EINVAL); nothing is synchronised, so the step can be captured in a
  * graph. */

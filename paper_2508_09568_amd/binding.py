@@ -355,8 +355,8 @@ class Bunch:
         """One local time step (see include/mhd_bunch.h): ready patches fill their guards at
         their own time from the owners' two slices and advance by their own CFL step (or
         dt_fixed; rounded down to dt_quantum x 2^k if dt_quantum > 0) clipped to t_end; the
-        others stay.  t, t_prev and dt (written) are (P,) float64 device tensors.  The caller
-        swaps U_cur and U_new afterwards."""
+        others stay.  t, t_prev and dt (written) are (P,) float64 device tensors.  U_new is
+        scratch; on return U_cur holds every patch at its own time."""
         for x, what in ((U_cur, "U_cur"), (U_new, "U_new"), (U_prev, "U_prev")):
             self._check_state(x, what)
         for x, what in ((t, "t"), (t_prev, "t_prev"), (dt, "dt")):

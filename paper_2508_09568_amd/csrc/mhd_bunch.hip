@@ -140,14 +140,14 @@ __global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS))
 __attribute__((amdgpu_waves_per_eu(SolveWaves<T, TX, TY, TZ, FORM>::value))) void k_solve(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, const T* __restrict__ Uin,
     T* __restrict__ Uout, const T* __restrict__ S, const double* __restrict__ dt,
-    const double* __restrict__ dx, Consts<T> c, int g, int ntile, int remap) {
+    const double* __restrict__ dx, Consts<T> c, int g, int ntile, int remap, int copy_rest) {
   __shared__ T lds[TileShape<TX, TY, TZ>::template Lds<FORM>::value];
   DevX ex;
   for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
     const TileDev tl = tiles[logical_block(vb, ntile, remap)];
     const PatchDev& P = pt[tl.patch];
     if (dt[tl.patch] == 0.0) {  // a patch at rest this step: its owned values are copied
-      copy_tile<TX, TY, TZ>(ex, P, g, tl, Uin, Uout);
+      if (copy_rest) copy_tile<TX, TY, TZ>(ex, P, g, tl, Uin, Uout);
       continue;
     }
     solve_tile<T, TX, TY, TZ, FORM>(ex, lds, P, g, tl, Uin, Uout, S, dt[tl.patch],
@@ -321,11 +321,12 @@ __global__ __launch_bounds__(BLK) void k_lts_dt(const int32_t* __restrict__ read
   dt[p] = ready[p] ? (d < rest ? d : rest) : 0.0;
 }
 
-// previous slice of every ready patch <- its state before the step (all padded cells)
+// every ready patch: previous slice <- its state before the step (all padded cells), then
+// its owned values <- the update's result (patches at rest are touched by neither)
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_lts_keep(const PatchDev* __restrict__ pt,
-                                                  const BoxBlock* __restrict__ blk,
-                                                  const T* __restrict__ U, T* __restrict__ Uprev,
+                                                  const BoxBlock* __restrict__ blk, T* U,
+                                                  const T* __restrict__ Unew, T* __restrict__ Uprev,
                                                   const int32_t* __restrict__ ready, int g) {
   const BoxBlock b = blk[blockIdx.x];
   if (!ready[b.patch]) return;
@@ -333,7 +334,12 @@ __global__ __launch_bounds__(BLK) void k_lts_keep(const PatchDev* __restrict__ p
   int x[3];
   if (!decode(P, BOX_ALL, g, b.first, x[0], x[1], x[2])) return;
   const int64_t cell = cell_of(P, x[0], x[1], x[2]);
-  for (int m = 0; m < 8; ++m) Uprev[P.ubase + m * P.Nc + cell] = U[P.ubase + m * P.Nc + cell];
+  const bool own = owned(P, g, x);
+  for (int m = 0; m < 8; ++m) {
+    const int64_t e = P.ubase + m * P.Nc + cell;
+    Uprev[e] = U[e];
+    if (own) U[e] = Unew[e];
+  }
 }
 
 // time of every ready patch advances by its step; a step clipped to t_end ends exactly there
@@ -548,6 +554,7 @@ struct mhd_bunch {
   size_t o_ptiles[MAXPSHAPE] = {0};
   int64_t scratch_elems = 0;
   size_t o_ready = 0;  // local time stepping: ready flag per patch (int32)
+  bool copy_rest = true;  // update: copy patches at rest (false inside a local time step)
   size_t o_pt = 0, o_blk[NBOX] = {0}, o_tiles[MAXSHAPE] = {0}, o_smax = 0, o_status = 0,
          o_scratch = 0;
   // mhd_bunch_graph_capture: instantiated graph of a multi-step run
@@ -676,7 +683,8 @@ void solve_launch(mhd_bunch* h, int nt, const TileDev* tl, const T* Uin, T* Uout
     grid = h->persistent_grid(nt, occ);
   }
   hipLaunchKernelGGL((k_solve<T, X, Y, Z, FORM>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0,
-                     s, h->d_pt(), tl, Uin, Uout, S, dt, dx, c, h->g, nt, h->mode >= 1);
+                     s, h->d_pt(), tl, Uin, Uout, S, dt, dx, c, h->g, nt, h->mode >= 1,
+                     h->copy_rest ? 1 : 0);
 }
 
 template <typename T, int X, int Y, int Z>
@@ -930,11 +938,13 @@ mhd_status launch_lts_step(mhd_bunch* h, T* Ucur, T* Unew, T* Uprev, double* t, 
   }
   hipLaunchKernelGGL(k_lts_dt, dim3(pg), dim3(BLK), 0, s, (const int32_t*)ready, (const double*)t,
                      t_end, quantum, dt_fixed ? dt_fixed : (const double*)dt, dt, h->P);
+  h->copy_rest = false;  // U_new is scratch: only the ready patches' results are kept
   const mhd_status st = launch_update<T>(h, (const T*)Ucur, Unew, dt, dx, s);
+  h->copy_rest = true;
   if (st != MHD_OK) return st;
   const int na = (int)h->blocks[BOX_ALL].size();
-  hipLaunchKernelGGL(k_lts_keep<T>, dim3(na), dim3(BLK), 0, s, h->d_pt(), h->d_blk(BOX_ALL),
-                     (const T*)Ucur, Uprev, (const int32_t*)ready, h->g);
+  hipLaunchKernelGGL(k_lts_keep<T>, dim3(na), dim3(BLK), 0, s, h->d_pt(), h->d_blk(BOX_ALL), Ucur,
+                     (const T*)Unew, Uprev, (const int32_t*)ready, h->g);
   hipLaunchKernelGGL(k_lts_time, dim3(pg), dim3(BLK), 0, s, (const int32_t*)ready, t, tprev,
                      (const double*)dt, t_end, h->P);
   return h->hip_ok(hipGetLastError(), "launch local time step") ? MHD_OK : MHD_EDEVICE;

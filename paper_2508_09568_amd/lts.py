@@ -24,7 +24,6 @@ def run(bunch, U, dx, nbr, t_end, dt_fixed=None, dt_quantum=0.0, check_every=16,
         bunch.lts_step(Ua, Ub, Up, t, tp, dt, dx, nbr, t_end, dt_fixed=dt_fixed,
                        dt_quantum=dt_quantum)
         count += dt > 0
-        Ua, Ub = Ub, Ua
         n += 1
         if n % check_every == 0 and bool((t >= t_end).all()):
             break

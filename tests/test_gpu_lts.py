@@ -49,8 +49,22 @@ def test_one_step_fill_and_bookkeeping_match_oracle_bitwise(precision):
                dt_fixed=dtf)
     assert B.check() == 0
     want = ref.astype(np.float32) if precision == 4 else ref
-    assert np.array_equal(host(Uc), want)                 # guards of the ready patches only
+    got = host(Uc)
+    Uin = U.astype(want.dtype)
+    for p in range(L.P):                                  # patches at rest untouched
+        if not ready[p]:
+            assert np.array_equal(L.view(got, p), L.view(Uin, p)), p
+    guard = np.ones(L.total, dtype=bool)
+    for p in range(L.P):
+        L.interior(guard, p)[...] = False
+    rmask = np.repeat(ready, np.diff(L.base))
+    assert np.array_equal(got[guard & rmask], want[guard & rmask])   # interpolated guards
+    assert not np.array_equal(got[~guard & rmask], Uin[~guard & rmask])  # interiors advanced
     dt_want = np.where(ready, np.minimum(1e-5, t_end - t), 0.0)
+    if precision == 8:                                    # ... by the update of the filled state
+        adv = oracle.step_many(ref, L.dims, L.g, dt_want, w.dx, oracle.Params(gamma=w.gamma))
+        err = rel_err_fields(L, got, adv, patches=np.nonzero(ready)[0])
+        assert err.max() <= 1e-12, err
     assert np.array_equal(host(dtd), dt_want)
     assert np.array_equal(host(tpd), np.where(ready, t, tp))
     assert np.array_equal(host(td), np.where(ready & (dt_want >= t_end - t), t_end, t + dt_want))
