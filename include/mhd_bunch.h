@@ -136,8 +136,8 @@ mhd_status mhd_bunch_cfl(mhd_bunch* h, const void* U_dev, const double* dx_dev,
  * t = t_prev (one slice per patch) and U_prev any buffer of the right size.  The run is over
  * when every t[p] == t_end.  The three
  * state buffers must not overlap, t, t_prev and dt must be distinct and dt_quantum must be
- * finite and >= 0 (MHD_EINVAL); nothing is synchronised, so the step can be captured in a
- * graph. */
+ * finite and >= 0 (MHD_EINVAL).  Only kernels are enqueued (no host synchronisation, no
+ * memset or copy calls). */
 mhd_status mhd_bunch_lts_step(mhd_bunch* h, void* U_cur, void* U_new, void* U_prev, double* t_dev,
                               double* t_prev_dev, double* dt_dev, const double* dt_fixed_dev,
                               const double* dx_dev, const int32_t* nbr_dev, double t_end,
