@@ -136,6 +136,31 @@ def test_predictor_modes_are_listed_and_range_checked(B, dims, shapes):
         B.mhd_bunch_destroy(h)
 
 
+def test_local_time_step_validates_its_arguments_on_the_host(B):
+    """mhd_bunch_lts_step rejects missing or aliased time arrays, a negative or non-finite
+    quantum and a NaN end time before any launch, and needs a bound handle."""
+    rc, h = _create(B, [[16, 16, 16]] * 2)
+    assert rc == B.MHD_OK
+    bufs = [np.zeros(8) for _ in range(9)]
+    U0, U1, U2, t, tp, dt, dtf, dx, nbr = (C.c_void_p(b.ctypes.data) for b in bufs)
+    try:
+        def call(**kw):
+            a = dict(U_cur=U0, U_new=U1, U_prev=U2, t=t, t_prev=tp, dt=dt, dt_fixed=dtf, dx=dx,
+                     nbr=nbr, t_end=1.0, q=0.0)
+            a.update(kw)
+            return B.mhd_bunch_lts_step(h, a["U_cur"], a["U_new"], a["U_prev"], a["t"],
+                                        a["t_prev"], a["dt"], a["dt_fixed"], a["dx"], a["nbr"],
+                                        a["t_end"], a["q"], None)
+        for kw in (dict(U_cur=None), dict(t=None), dict(nbr=None), dict(t_prev=t), dict(dt=t),
+                   dict(dt=tp), dict(q=-1.0), dict(q=float("nan")), dict(q=float("inf")),
+                   dict(t_end=float("nan"))):
+            assert call(**kw) == B.MHD_EINVAL, kw
+        assert call() == B.MHD_ESTATE                      # valid, but the handle is not bound
+        assert call(dt_fixed=None, q=0.5) == B.MHD_ESTATE
+    finally:
+        B.mhd_bunch_destroy(h)
+
+
 def test_status_strings(B):
     for code in range(-6, 1):
         assert B.mhd_status_string(code)
