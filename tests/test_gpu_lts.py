@@ -146,3 +146,34 @@ def test_time_levels_match_oracle_driver():
     err = rel_err_fields(L, host(Ug), Uo)
     log(f"    {ns} steps, updates per patch {cnt.min()}..{cnt.max()}: rel err {err.max():.2e}")
     assert err.max() <= 1e-12 * cnt.max(), err
+
+
+def test_fp32_run_with_fixed_steps_against_fp64_oracle():
+    """The same fixed-step schedule in FP32 (times and steps stay FP64): same updates per
+    patch, states within the FP32 full-run bar of the FP64 oracle."""
+    import oracle
+    import torch
+    from paper_2508_09568_amd import lts
+    log("[gpu] lts run fp32 vs fp64 oracle, fixed per-patch steps")
+    w, U = _ot()
+    L = w.layout
+    U = U.astype(np.float32).astype(np.float64)
+    prm = oracle.Params(gamma=w.gamma)
+    dtf = 1e-3 * 2.0 ** -(np.arange(L.P) % 3)
+    t_end = 4e-3
+    Uo, to, cnt, ns = oracle.lts_run(U, L.dims, L.g, w.dx, w.nbr, prm, t_end=t_end, dt_fixed=dtf)
+    B = make_bunch(L, w.gamma, precision=4)
+    Ug, tg, n, cg = lts.run(B, dev(U).to(torch.float32), dev(w.dx), dev(w.nbr.astype(np.int32)),
+                            t_end, dt_fixed=dev(dtf), check_every=1)
+    assert B.check() == 0
+    assert n == ns and np.array_equal(host(cg), cnt) and np.array_equal(host(tg), to)
+    G = host(Ug).astype(np.float64)
+    num = np.zeros(8)
+    den = np.zeros(8)
+    for p in range(L.P):
+        a, b = L.interior(G, p).reshape(8, -1), L.interior(Uo, p).reshape(8, -1)
+        num += np.abs(a - b).sum(axis=1)
+        den += np.abs(b).sum(axis=1)
+    err = num / np.maximum(den, 1e-300)
+    log(f"    FP32 L1 rel err per field: {err}")
+    assert err.max() <= 1e-5, err
