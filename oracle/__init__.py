@@ -84,6 +84,7 @@ def lib():
         L.mhd_oracle_fill_guards_at.argtypes = [C.c_int32, ip, C.c_int32, dp, dp, dp, dp, ip, ip]
         L.mhd_oracle_count_ops.argtypes = [ip, C.c_int32, dp, C.c_double, dp, P(_Params), lp]
         L.mhd_oracle_hlld.argtypes = [dp, dp, P(_Params), dp, ip]
+        L.mhd_oracle_hlld_fan.argtypes = [dp, dp, P(_Params), dp, ip, dp, dp]
         L.mhd_oracle_cfast.argtypes = [C.c_double] * 6
         L.mhd_oracle_cfast.restype = C.c_double
         L.mhd_oracle_limiter.argtypes = [C.c_double, C.c_double, C.c_int32]
@@ -339,6 +340,20 @@ def hlld(L, R, prm: Params):
     p = prm.c()
     lib().mhd_oracle_hlld(_d(L), _d(R), C.byref(p), _d(F), _i(reg))
     return F, int(reg[0])
+
+
+def hlld_fan(L, R, prm: Params):
+    """HLLD flux with its wave fan: (F, region, speeds (S_L, S*_L, S_M, S*_R, S_R, and
+    the total pressure of the intermediate states), states (U*_L, U**_L, U**_R, U*_R) as
+    rows (rho, m_n, m_t1, m_t2, E, B_n, B_t1, B_t2))."""
+    L, R = _f64(L), _f64(R)
+    F = np.empty(5, dtype=np.float64)
+    reg = np.zeros(1, dtype=np.int32)
+    sp = np.empty(6, dtype=np.float64)
+    st = np.empty((4, 8), dtype=np.float64)
+    p = prm.c()
+    lib().mhd_oracle_hlld_fan(_d(L), _d(R), C.byref(p), _d(F), _i(reg), _d(sp), _d(st))
+    return F, int(reg[0]), sp, st
 
 
 def cfast(rho, p, bn, bt1, bt2, gamma):

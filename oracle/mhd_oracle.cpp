@@ -145,7 +145,8 @@ S limiter(S dl, S dr, int type) {
  * B_t1, B_t2); B_n is shared by both sides.  Returns (rho, m_n, m_t1, m_t2, E) fluxes of
  * the x-flux vector of eq:MHD_vector written in the face frame. */
 template <class S>
-void hlld(const S L[8], const S R[8], const mhd_oracle_params& P, S F[5], int* region) {
+void hlld(const S L[8], const S R[8], const mhd_oracle_params& P, S F[5], int* region,
+          double* fan_speeds = nullptr, double (*fan_states)[8] = nullptr) {
   const double gam = P.gamma;
   const S bn = L[5];
   const S rl = L[0], ul = L[1], vl = L[2], wl = L[3], pl = L[4], byl = L[6], bzl = L[7];
@@ -243,6 +244,23 @@ void hlld(const S L[8], const S R[8], const mhd_oracle_params& P, S F[5], int* r
   else { sel = FR; reg = 5; }
   for (int m = 0; m < 5; ++m) F[m] = sel[m];
   if (region) *region = reg;
+  // optional record of the wave fan (speeds S_L, S*_L, S_M, S*_R, S_R, the total pressure
+  // of the four intermediate states, and the states U*_L, U**_L, U**_R, U*_R as (rho, m_n,
+  // m_t1, m_t2, E, B_n, B_t1, B_t2))
+  if (fan_speeds) {
+    const S sp[6] = {sl, ssl, sm, ssr, sr, pts};
+    for (int k = 0; k < 6; ++k) fan_speeds[k] = val(sp[k]);
+  }
+  if (fan_states) {
+    const S* U4[4] = {UsL, UssL, UssR, UsR};
+    const S bt[4][2] = {{stl.by, stl.bz}, {byss, bzss}, {byss, bzss}, {str.by, str.bz}};
+    for (int k = 0; k < 4; ++k) {
+      for (int m = 0; m < 5; ++m) fan_states[k][m] = val(U4[k][m]);
+      fan_states[k][5] = val(bn);
+      fan_states[k][6] = val(bt[k][0]);
+      fan_states[k][7] = val(bt[k][1]);
+    }
+  }
 }
 
 /* Edge EMF from the four predicted corner states around an edge along e (§2.1,
@@ -930,6 +948,13 @@ void mhd_oracle_hlld(const double L[8], const double R[8], const mhd_oracle_para
                      double F[5], int32_t* region) {
   int reg = -1;
   hlld(L, R, *prm, F, &reg);
+  if (region) *region = reg;
+}
+
+void mhd_oracle_hlld_fan(const double L[8], const double R[8], const mhd_oracle_params* prm,
+                         double F[5], int32_t* region, double speeds[6], double states[4][8]) {
+  int reg = -1;
+  hlld(L, R, *prm, F, &reg, speeds, states);
   if (region) *region = reg;
 }
 

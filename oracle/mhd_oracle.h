@@ -117,6 +117,13 @@ int mhd_oracle_ops_per_cell(const int32_t n[3], int32_t g, const double* U_in, d
 void mhd_oracle_hlld(const double L[8], const double R[8], const mhd_oracle_params* prm,
                      double F[5], int32_t* region);
 
+/* The same flux with the wave fan it was built from: speeds[6] = (S_L, S*_L, S_M, S*_R,
+ * S_R, total pressure of the intermediate states) and states[4] = U*_L, U**_L, U**_R, U*_R,
+ * each (rho, m_n, m_t1, m_t2, E, B_n, B_t1, B_t2) in the face frame.  For checks of the
+ * jump conditions across every wave. */
+void mhd_oracle_hlld_fan(const double L[8], const double R[8], const mhd_oracle_params* prm,
+                         double F[5], int32_t* region, double speeds[6], double states[4][8]);
+
 /* Fast magnetosonic speed along a direction with normal field bn. */
 double mhd_oracle_cfast(double rho, double p, double bn, double bt1, double bt2, double gamma);
 

@@ -227,3 +227,31 @@ def hll_transverse_flux(WL, WR, SLm, SRp):
     FR = WR[6] * WR[1] - WR[5] * WR[2]
     ap, am = SRp, SLm
     return (ap * FL + am * FR - ap * am * (WR[6] - WL[6])) / (ap + am)
+
+
+def cfast_textbook(rho, p, bn, bt1, bt2, gamma):
+    """Fast magnetosonic speed in its usual closed form,
+    c_f^2 = (a^2 + b^2 + sqrt((a^2 + b^2)^2 - 4 a^2 b_n^2)) / 2 with a^2 = gamma p / rho,
+    b^2 = |B|^2 / rho, b_n^2 = B_n^2 / rho."""
+    a2 = gamma * p / rho
+    b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) / rho
+    bn2 = bn * bn / rho
+    return math.sqrt(0.5 * (a2 + b2 + math.sqrt((a2 + b2) ** 2 - 4.0 * a2 * bn2)))
+
+
+def face_flux8(U, gamma, pt=None):
+    """All 8 components of the physical flux along the face normal (x) of a face-frame
+    conserved state U = (rho, m_n, m_t1, m_t2, E, B_n, B_t1, B_t2).  pt: total pressure
+    to use instead of the one of the energy relation (intermediate states of an
+    approximate Riemann fan carry their own total pressure)."""
+    U = np.asarray(U, dtype=float)
+    F = mhd_flux(U, 0, gamma)
+    if pt is not None:
+        rho = U[0]
+        u = U[1] / rho
+        b2 = U[5] ** 2 + U[6] ** 2 + U[7] ** 2
+        pg = (gamma - 1.0) * (U[4] - 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / rho - 0.5 * b2)
+        d = pt - (pg + 0.5 * b2)
+        F[1] += d
+        F[4] += u * d
+    return F
