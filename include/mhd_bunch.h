@@ -132,11 +132,13 @@ mhd_status mhd_bunch_cfl(mhd_bunch* h, const void* U_dev, const double* dx_dev,
  *  5. for every ready patch: U_prev <- U_cur (its whole padded block), then U_cur's owned
  *     cells and faces <- U_new's, t_prev[p] = t[p], t[p] += dt[p] (exactly t_end when the
  *     step was clipped to it).
+ * A ready patch whose step (given or its own CFL step) is not finite and > 0 gets dt[p] = 0,
+ * stays where it is and raises a status bit that mhd_bunch_check reports as MHD_EINVAL.
  * On return U_cur holds every patch at its time t[p] (no buffers to swap).  Start with
  * t = t_prev (one slice per patch) and U_prev any buffer of the right size.  The run is over
  * when every t[p] == t_end.  The three
- * state buffers must not overlap, t, t_prev and dt must be distinct and dt_quantum must be
- * finite and >= 0 (MHD_EINVAL).  Only kernels are enqueued (no host synchronisation, no
+ * state buffers must not overlap, t, t_prev, dt and dt_fixed must be distinct, dt_fixed must
+ * hold finite steps > 0 and dt_quantum must be finite and >= 0 (MHD_EINVAL).  Only kernels are enqueued (no host synchronisation, no
  * memset or copy calls). */
 mhd_status mhd_bunch_lts_step(mhd_bunch* h, void* U_cur, void* U_new, void* U_prev, double* t_dev,
                               double* t_prev_dev, double* dt_dev, const double* dt_fixed_dev,
@@ -223,7 +225,10 @@ mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* U_in, void* U_out, const
  *   nbr_dev != NULL: the guards of the step's input filled first (as mhd_bunch_fill_guards);
  *                    NULL: guards are frozen inputs;
  *   dt_mode 0: dt_dev used as given; 1: dt_dev[p] = the patch's own CFL step of the step's
- *              input (local time stepping, each patch at its own dt); 2: global minimum.
+ *              input (each patch steps independently at its own dt: valid with frozen
+ *              guards only, so nbr_dev must be NULL, else MHD_EINVAL -- a guard exchange
+ *              between patches at different times needs mhd_bunch_lts_step); 2: global
+ *              minimum.
  * Every launch of every step uses the launch configuration current at capture time.
  * Buffers are bound by address: they must stay allocated while the graph is launched.
  * Capture uses a private stream; nothing runs until mhd_bunch_graph_launch enqueues the
@@ -234,7 +239,9 @@ mhd_status mhd_bunch_graph_capture(mhd_bunch* h, int32_t nsteps, void* U_a, void
 mhd_status mhd_bunch_graph_launch(mhd_bunch* h, hipStream_t stream);
 
 /* Synchronises `stream`, then returns MHD_ENONPHYS if any kernel since the last check
- * met a non-physical state (and clears the flag), else MHD_OK. */
+ * met a non-physical state, MHD_EINVAL if a guard fill met an inconsistent neighbour table or
+ * a local time step met a step that is not finite and > 0 (and clears the flags), else
+ * MHD_OK. */
 mhd_status mhd_bunch_check(mhd_bunch* h, hipStream_t stream);
 
 /* Kernel timing with HIP events recorded on the caller's stream around every launch.

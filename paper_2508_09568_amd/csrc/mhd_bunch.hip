@@ -305,20 +305,24 @@ __global__ __launch_bounds__(BLK) void k_guards_at(const PatchDev* __restrict__ 
 // step of each patch: its own (or the given) step, rounded down to quantum x 2^k when a
 // quantum is given (time levels: exact powers of two, frexp is exact), clipped to t_end when
 // ready, else zero
+// A ready patch whose step is not finite and positive (a non-finite state, or a bad given
+// step) does not advance: its step is 0 and status bit 4 is raised.
 __global__ __launch_bounds__(BLK) void k_lts_dt(const int32_t* __restrict__ ready,
                                                 const double* __restrict__ t, double t_end,
                                                 double quantum, const double* src, double* dt,
-                                                int np) {
+                                                int np, int* status) {
   const int p = blockIdx.x * BLK + threadIdx.x;
   if (p >= np) return;
   double d = src[p];
-  if (quantum > 0.0) {
+  const bool good = d > 0.0 && d <= 1.7976931348623157e308;
+  if (quantum > 0.0 && good) {
     int e;
     (void)frexp(d / quantum, &e);  // d / quantum in [2^(e-1), 2^e)
     d = ldexp(quantum, e - 1);
   }
   const double rest = t_end - t[p];
-  dt[p] = ready[p] ? (d < rest ? d : rest) : 0.0;
+  if (ready[p] && !good) atomicOr(status, 4);
+  dt[p] = ready[p] && good ? (d < rest ? d : rest) : 0.0;
 }
 
 // every ready patch: previous slice <- its state before the step (all padded cells), then
@@ -461,6 +465,8 @@ __global__ __launch_bounds__(BLK) void k_adj_fold(const PatchDev* __restrict__ p
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+
 
 // Solver tile shapes per activity pattern (bit d set = direction d active), the first one
 // the default.  The lists drive both the host-side tables and the kernel instantiations.
@@ -736,11 +742,11 @@ void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uou
 #undef MHD_TRY
 }
 
+// S: scratch of one chunk of patches
 template <typename T>
 mhd_status launch_update(mhd_bunch* h, const T* Uin, T* Uout, const double* dt, const double* dx,
-                         hipStream_t s) {
+                         hipStream_t s, T* S) {
   const Consts<T> c = h->consts<T>();
-  T* S = (T*)h->d_scratch();
   const int rm = h->mode >= 1;
   for (const auto& ch : h->chunks) {
     hipEvent_t t0;
@@ -937,9 +943,10 @@ mhd_status launch_lts_step(mhd_bunch* h, T* Ucur, T* Unew, T* Uprev, double* t, 
     if (st != MHD_OK) return st;
   }
   hipLaunchKernelGGL(k_lts_dt, dim3(pg), dim3(BLK), 0, s, (const int32_t*)ready, (const double*)t,
-                     t_end, quantum, dt_fixed ? dt_fixed : (const double*)dt, dt, h->P);
+                     t_end, quantum, dt_fixed ? dt_fixed : (const double*)dt, dt, h->P,
+                     h->d_status());
   h->copy_rest = false;  // U_new is scratch: only the ready patches' results are kept
-  const mhd_status st = launch_update<T>(h, (const T*)Ucur, Unew, dt, dx, s);
+  const mhd_status st = launch_update<T>(h, (const T*)Ucur, Unew, dt, dx, s, (T*)h->d_scratch());
   h->copy_rest = true;
   if (st != MHD_OK) return st;
   const int na = (int)h->blocks[BOX_ALL].size();
@@ -1301,8 +1308,10 @@ mhd_status mhd_bunch_update(mhd_bunch* h, const void* Uin, void* Uout, const dou
   const size_t bytes = (size_t)h->state_elems * h->prec;
   const char *a = (const char*)Uin, *b = (const char*)Uout;
   if (a < b + bytes && b < a + bytes) return MHD_EINVAL;
-  return h->prec == 8 ? launch_update<double>(h, (const double*)Uin, (double*)Uout, dt, dx, s)
-                      : launch_update<float>(h, (const float*)Uin, (float*)Uout, dt, dx, s);
+  return h->prec == 8 ? launch_update<double>(h, (const double*)Uin, (double*)Uout, dt, dx, s,
+                                              (double*)h->d_scratch())
+                      : launch_update<float>(h, (const float*)Uin, (float*)Uout, dt, dx, s,
+                                             (float*)h->d_scratch());
 }
 
 mhd_status mhd_bunch_lts_step(mhd_bunch* h, void* U_cur, void* U_new, void* U_prev, double* t,
@@ -1311,6 +1320,7 @@ mhd_status mhd_bunch_lts_step(mhd_bunch* h, void* U_cur, void* U_new, void* U_pr
                               double dt_quantum, hipStream_t s) {
   if (!h || !U_cur || !U_new || !U_prev || !t || !t_prev || !dt || !dx || !nbr) return MHD_EINVAL;
   if (!(t_end == t_end) || t == t_prev || dt == t || dt == t_prev) return MHD_EINVAL;
+  if (dt_fixed && (dt_fixed == dt || dt_fixed == t || dt_fixed == t_prev)) return MHD_EINVAL;
   if (!(dt_quantum >= 0.0) || dt_quantum > 1e300) return MHD_EINVAL;
   if (!h->bound) return MHD_ESTATE;
   const size_t bytes = (size_t)h->state_elems * h->prec;
@@ -1336,7 +1346,7 @@ mhd_status mhd_bunch_check(mhd_bunch* h, hipStream_t s) {
     const int zero = 0;
     if (hipMemcpy(h->ws + h->o_status, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
       return MHD_EDEVICE;
-    return (st & 2) ? MHD_EINVAL : MHD_ENONPHYS;
+    return (st & 6) ? MHD_EINVAL : MHD_ENONPHYS;
   }
   return MHD_OK;
 }
@@ -1470,6 +1480,7 @@ mhd_status mhd_bunch_graph_capture(mhd_bunch* h, int32_t nsteps, void* U_a, void
                                    hipStream_t s) {
   (void)s;
   if (!h || nsteps < 1 || !U_a || !U_b || !dt || !dx || dt_mode < 0 || dt_mode > 2) return MHD_EINVAL;
+  if (dt_mode == 1 && nbr) return MHD_EINVAL;  // neighbours at other times: use mhd_bunch_lts_step
   if (!h->bound) return MHD_ESTATE;
   const size_t bytes = (size_t)h->state_elems * h->prec;
   const char *pa = (const char*)U_a, *pb = (const char*)U_b;

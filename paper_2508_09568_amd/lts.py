@@ -10,8 +10,12 @@ import torch
 def run(bunch, U, dx, nbr, t_end, dt_fixed=None, dt_quantum=0.0, check_every=16,
         max_steps=1_000_000):
     """Advance the state tensor U (guards filled or not) to t_end; dt_quantum > 0 rounds every
-    step down to dt_quantum x 2^k (time levels).  Returns (U at t_end, t (all t_end), number
-    of steps, updates per patch)."""
+    step down to dt_quantum x 2^k (time levels).  Every `check_every` steps the host reads
+    the device status (raising on a non-physical state, a bad neighbour table or a step that
+    is not finite and > 0) and the patch times.  Returns (U at t_end, t (all t_end), number
+    of steps in which some patch advanced, updates per patch); the launches after the last
+    such step (at most check_every - 1, none of which changes anything) are not counted."""
+    from .binding import MhdError
     P = bunch.P
     dev = U.device
     Ua, Ub, Up = U.clone(), torch.empty_like(U), U.clone()
@@ -19,14 +23,21 @@ def run(bunch, U, dx, nbr, t_end, dt_fixed=None, dt_quantum=0.0, check_every=16,
     tp = torch.zeros(P, dtype=torch.float64, device=dev)
     dt = torch.zeros(P, dtype=torch.float64, device=dev)
     count = torch.zeros(P, dtype=torch.int64, device=dev)
+    nwork = torch.zeros((), dtype=torch.int64, device=dev)
     n = 0
     while n < max_steps:
         bunch.lts_step(Ua, Ub, Up, t, tp, dt, dx, nbr, t_end, dt_fixed=dt_fixed,
                        dt_quantum=dt_quantum)
-        count += dt > 0
+        adv = dt > 0
+        count += adv
+        nwork += adv.any()
         n += 1
-        if n % check_every == 0 and bool((t >= t_end).all()):
-            break
+        if n % check_every == 0:
+            rc = bunch.check()
+            if rc != 0:
+                raise MhdError(rc, "lts.run: device status after step %d" % n)
+            if bool((t >= t_end).all()):
+                break
     else:
         raise RuntimeError("lts.run: step limit reached")
-    return Ua, t, n, count
+    return Ua, t, int(nwork.item()), count

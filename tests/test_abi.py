@@ -155,6 +155,8 @@ def test_local_time_step_validates_its_arguments_on_the_host(B):
                    dict(dt=tp), dict(q=-1.0), dict(q=float("nan")), dict(q=float("inf")),
                    dict(t_end=float("nan"))):
             assert call(**kw) == B.MHD_EINVAL, kw
+        for kw in (dict(dt_fixed=dt), dict(dt_fixed=t), dict(dt_fixed=tp)):
+            assert call(**kw) == B.MHD_EINVAL, kw         # the given steps alias written arrays
         assert call() == B.MHD_ESTATE                      # valid, but the handle is not bound
         assert call(dt_fixed=None, q=0.5) == B.MHD_ESTATE
     finally:
@@ -164,3 +166,20 @@ def test_local_time_step_validates_its_arguments_on_the_host(B):
 def test_status_strings(B):
     for code in range(-6, 1):
         assert B.mhd_status_string(code)
+
+
+def test_graph_of_own_steps_with_guard_exchange_is_refused(B):
+    """Each patch at its own CFL step in a captured run needs frozen guards: exchanging guards
+    between patches at different times is what mhd_bunch_lts_step does."""
+    rc, h = _create(B, [[16, 16, 16]] * 2)
+    assert rc == B.MHD_OK
+    bufs = [np.zeros(8) for _ in range(5)]
+    Ua, Ub, dt, dx, nbr = (C.c_void_p(b.ctypes.data) for b in bufs)
+    try:
+        assert B.mhd_bunch_graph_capture(h, 2, Ua, Ub, dt, dx, nbr, 1, None) == B.MHD_EINVAL
+        # the same run with frozen guards, or with a global step, only lacks the binding
+        assert B.mhd_bunch_graph_capture(h, 2, Ua, Ub, dt, dx, None, 1, None) == B.MHD_ESTATE
+        assert B.mhd_bunch_graph_capture(h, 2, Ua, Ub, dt, dx, nbr, 2, None) == B.MHD_ESTATE
+    finally:
+        B.mhd_bunch_destroy(h)
+

@@ -17,10 +17,15 @@ def _ragged(seed_noise=0):
     return w.layout, w.U.numpy().copy(), np.ascontiguousarray(w.dx), w.gamma
 
 
-@pytest.mark.parametrize("case", ["ragged3d", "ot64", "sod"])
-def test_every_launch_configuration_gives_identical_bits(case):
+@pytest.mark.parametrize("case,precision", [("ragged3d", 8), ("ot64", 8), ("sod", 8),
+                                            ("ragged3d", 4), ("ot64", 4), ("sod", 4)])
+def test_every_launch_configuration_gives_identical_bits(case, precision):
+    """In either precision every configuration gives the bits of every other; the common
+    result is within the per-step bar of the oracle (FP64 1e-12; FP32 2e-5 against the
+    oracle's update of the same FP32-rounded state)."""
     import oracle
-    log(f"[gpu] launch configurations case={case}")
+    import torch
+    log(f"[gpu] launch configurations case={case} precision={precision}")
     if case == "ragged3d":
         L, U, dx, gam = _ragged()
     elif case == "ot64":
@@ -31,13 +36,16 @@ def test_every_launch_configuration_gives_identical_bits(case):
         w = W.sod(128, patches=2)
         L, U, dx, gam = w.layout, w.U.copy(), w.dx, w.gamma
         oracle.fill_guards(U, L.dims, L.g, w.nbr)
+    if precision == 4:
+        U = U.astype(np.float32).astype(np.float64)
     prm = oracle.Params(gamma=gam)
     dt = oracle.cfl_many(U, L.dims, L.g, dx, prm)
     ref = oracle.step_many(U, L.dims, L.g, dt, dx, prm)
-    B = make_bunch(L, gam)
+    B = make_bunch(L, gam, precision=precision)
     cfgs = B.tile_configs()
     assert len(cfgs) >= 2 and B.tile() == 0
-    Ui, dtd, dxd = dev(U), dev(dt), dev(dx)
+    dty = torch.float64 if precision == 8 else torch.float32
+    Ui, dtd, dxd = dev(U).to(dty), dev(dt), dev(dx)
     # every other patch at rest (dt = 0): copied, while the others match the full update
     dtm = dt.copy()
     dtm[::2] = 0.0
@@ -54,7 +62,7 @@ def test_every_launch_configuration_gives_identical_bits(case):
             assert B.solver_split() == split
             for i, cfg in enumerate(cfgs):
                 B.set_tile(i)
-                Uo = dev(np.zeros_like(U))
+                Uo = torch.zeros_like(Ui)
                 B.update(Ui, Uo, dtd, dxd)
                 assert B.check() == 0
                 outs.append(host(Uo))
@@ -64,7 +72,7 @@ def test_every_launch_configuration_gives_identical_bits(case):
                     expect = outs[0].copy()
                     for p in range(0, L.P, 2):
                         L.interior(expect, p)[...] = L.interior(U, p)
-                Um = dev(np.zeros_like(U))
+                Um = torch.zeros_like(Ui)
                 B.update(Ui, Um, dtmd, dxd)
                 assert B.check() == 0
                 got = host(Um)
@@ -74,7 +82,8 @@ def test_every_launch_configuration_gives_identical_bits(case):
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     err = rel_err_fields(L, outs[0], ref)
-    assert err.max() <= 1e-12, err
+    log(f"    {len(outs)} configurations; per-field rel err vs oracle {err}")
+    assert err.max() <= (1e-12 if precision == 8 else 2e-5), err
 
 
 def test_autotune_picks_a_configuration_and_keeps_results():

@@ -177,3 +177,101 @@ def test_fp32_run_with_fixed_steps_against_fp64_oracle():
     err = num / np.maximum(den, 1e-300)
     log(f"    FP32 L1 rel err per field: {err}")
     assert err.max() <= 1e-5, err
+
+
+def _turb3d(case):
+    import oracle
+    if case == "periodic":
+        w = W.turbulence(N=64, patch=16)                 # 4^3 periodic patches of 16^3
+    else:
+        w = W.turbulence(N=64, patch=16, grid=(2, 2, 2))  # corner block: outflow faces
+    U = w.U.numpy().copy()
+    oracle.fill_guards(U, w.layout.dims, w.layout.g, w.nbr)
+    return w, U
+
+
+@pytest.mark.parametrize("case", ["periodic", "outflow_corner"])
+@pytest.mark.parametrize("sched", ["fixed", "levels"])
+def test_3d_runs_match_oracle_driver(case, sched):
+    """3D patches: readiness over all 26 neighbours, edge and corner guards interpolated from
+    diagonal owners, and (corner block) outflow guards whose owner is the patch itself.
+    Power-of-two fixed steps per patch (1, 1/2, 1/4 of a quantum), or each patch's own CFL
+    step halved per patch class and rounded down to quantum x 2^k: exact time sums, so the
+    schedule is the oracle's step for step and the states agree to rounding."""
+    import oracle
+    from paper_2508_09568_amd import lts
+    log(f"[gpu] lts 3D run vs oracle, case {case}, schedule {sched}")
+    w, U = _turb3d(case)
+    L = w.layout
+    prm = oracle.Params(gamma=w.gamma, cfl=w.cfl)
+    own = oracle.cfl_many(U, L.dims, L.g, w.dx, prm)
+    if sched == "fixed":
+        q = 2.0 ** np.floor(np.log2(float(own.min())))
+        dtf, quantum, t_end = q * 2.0 ** -(np.arange(L.P) % 3), 0.0, 4 * q
+    else:
+        dtf = own * 2.0 ** -(np.arange(L.P) % 3)
+        quantum = 2.0 ** np.floor(np.log2(float(dtf.min())))
+        t_end = 8 * quantum
+    Uo, to, cnt, ns = oracle.lts_run(U, L.dims, L.g, w.dx, w.nbr, prm, t_end=t_end,
+                                     dt_fixed=dtf, dt_quantum=quantum)
+    B = make_bunch(L, w.gamma)
+    Ug, tg, n, cg = lts.run(B, dev(U), dev(w.dx), dev(w.nbr.astype(np.int32)), t_end,
+                            dt_fixed=dev(dtf), dt_quantum=quantum, check_every=1)
+    assert B.check() == 0
+    assert n == ns and np.array_equal(host(cg), cnt) and np.array_equal(host(tg), to)
+    assert cnt.min() < cnt.max()                         # patches at different times
+    err = rel_err_fields(L, host(Ug), Uo)
+    log(f"    {ns} steps, updates per patch {cnt.min()}..{cnt.max()}: rel err {err.max():.2e}")
+    assert err.max() <= 1e-12 * cnt.max(), err
+
+
+def test_3d_fp32_run_against_fp64_oracle():
+    import oracle
+    import torch
+    from paper_2508_09568_amd import lts
+    log("[gpu] lts 3D fp32 run vs fp64 oracle, periodic, fixed steps")
+    w, U = _turb3d("periodic")
+    L = w.layout
+    U = U.astype(np.float32).astype(np.float64)
+    prm = oracle.Params(gamma=w.gamma, cfl=w.cfl)
+    own = oracle.cfl_many(U, L.dims, L.g, w.dx, prm)
+    q = 2.0 ** np.floor(np.log2(float(own.min())))
+    dtf = q * 2.0 ** -(np.arange(L.P) % 3)
+    Uo, to, cnt, ns = oracle.lts_run(U, L.dims, L.g, w.dx, w.nbr, prm, t_end=4 * q, dt_fixed=dtf)
+    B = make_bunch(L, w.gamma, precision=4)
+    Ug, tg, n, cg = lts.run(B, dev(U).to(torch.float32), dev(w.dx), dev(w.nbr.astype(np.int32)),
+                            4 * q, dt_fixed=dev(dtf), check_every=1)
+    assert B.check() == 0
+    assert n == ns and np.array_equal(host(cg), cnt) and np.array_equal(host(tg), to)
+    from gpu_util import l1_rel_fields
+    l1 = l1_rel_fields(L, host(Ug), Uo)
+    log(f"    FP32 L1 rel err per field: {l1}")
+    assert l1.max() <= 1e-5, l1
+
+
+def test_bad_given_step_stops_the_patch_and_is_reported():
+    """A ready patch whose given step is NaN, zero or negative does not advance (its state
+    and time stay, its step is 0) and the device status reports an invalid argument; the
+    other ready patches advance as usual."""
+    import torch
+
+    from paper_2508_09568_amd.binding import MHD_EINVAL
+    log("[gpu] lts step with NaN / zero / negative given steps")
+    w, U = _ot()
+    L = w.layout
+    B = make_bunch(L, w.gamma)
+    dtf = np.full(L.P, 1e-4)
+    dtf[[1, 5, 9]] = [np.nan, 0.0, -1e-4]
+    Uc, Un, Up = dev(U), dev(np.zeros_like(U)), dev(U)
+    t, tp, dt = (torch.zeros(L.P, dtype=torch.float64, device="cuda") for _ in range(3))
+    B.lts_step(Uc, Un, Up, t, tp, dt, dev(w.dx), dev(w.nbr.astype(np.int32)), 1.0,
+               dt_fixed=dev(dtf))
+    assert B.check() == MHD_EINVAL
+    assert B.check() == 0
+    th, dth, got = host(t), host(dt), host(Uc)
+    bad = np.zeros(L.P, dtype=bool)
+    bad[[1, 5, 9]] = True
+    assert np.all(dth[bad] == 0.0) and np.all(th[bad] == 0.0)
+    assert np.all(dth[~bad] == 1e-4) and np.all(th[~bad] == 1e-4)
+    for p in np.nonzero(bad)[0]:
+        assert np.array_equal(L.interior(got, p), L.interior(U, p))

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import mhdtest as mt
-from gpu_util import dev, host, l1_rel_fields, log, make_bunch, rel_err_fields
+from gpu_util import dev, host, l1_rel_fields, log, make_bunch, plain_rel_err_fields, rel_err_fields
 from paper_2508_09568_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -80,8 +80,11 @@ def test_step_parity_fp64(name):
     Uo = dev(np.zeros_like(U))
     B.update(Ui, Uo, dev(dt), dev(dx))
     assert B.check() == 0
-    err = rel_err_fields(L, host(Uo), ref)
+    got = host(Uo)
+    err = rel_err_fields(L, got, ref)
+    plain = plain_rel_err_fields(L, got, ref)
     log(f"    per-field rel err {err}")
+    log(f"    plain per-field relative max-norm (no natural-scale floor) {plain}")
     assert np.all(err <= FP64_STEP_TOL), err
 
 
@@ -290,7 +293,7 @@ def test_orszag_tang_run_fp64_matches_oracle():
     assert np.all(err <= 1e-10)
 
 
-@pytest.mark.parametrize("name,t_end,tol", [("sod", 0.2, 2e-6), ("ot64", 0.5, 1e-4)])
+@pytest.mark.parametrize("name,t_end,tol", [("sod", 0.2, 2e-6), ("ot64", 0.5, 1e-5)])
 def test_fp32_full_run_against_fp64_oracle(name, t_end, tol):
     import oracle
     log(f"[gpu] fp32 full run case={name} t_end={t_end}")
