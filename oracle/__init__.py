@@ -38,7 +38,8 @@ def build(force: bool = True) -> str:
 
 class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("rho_floor", C.c_double),
-                ("p_floor", C.c_double), ("eps_deg", C.c_double), ("limiter", C.c_int32)]
+                ("p_floor", C.c_double), ("eps_deg", C.c_double), ("limiter", C.c_int32),
+                ("emf_solver", C.c_int32)]
 
 
 @dataclass
@@ -49,10 +50,11 @@ class Params:
     p_floor: float = 1e-12
     eps_deg: float = 1e-10
     limiter: int = 0          # 0 = MC, 1 = minmod
+    emf_solver: int = 0       # edge EMF: 0 = UCT-HLL, 1 = UCT-HLLD
 
     def c(self) -> _Params:
         return _Params(self.gamma, self.cfl, self.rho_floor, self.p_floor, self.eps_deg,
-                       self.limiter)
+                       self.limiter, self.emf_solver)
 
 
 _lib = None
@@ -93,6 +95,8 @@ def lib():
         L.mhd_oracle_uct.restype = C.c_double
         L.mhd_oracle_dqdt.argtypes = [dp, dp, ip, C.c_double, dp]
         L.mhd_oracle_threads.restype = C.c_int
+        L.mhd_oracle_set_threads.argtypes = [C.c_int]
+        L.mhd_oracle_set_threads.restype = None
         L.mhd_oracle_ops_per_cell.argtypes = [ip, C.c_int32, dp, C.c_double, dp, P(_Params), dp]
         _lib = L
     return _lib
@@ -117,6 +121,11 @@ def _i32(a):
 def threads() -> int:
     """OpenMP threads used by the multi-patch entry points."""
     return int(lib().mhd_oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP threads of the multi-patch entry points."""
+    lib().mhd_oracle_set_threads(int(n))
 
 
 def step_many(U, dims, g, dt, dx, prm: Params, count_floors=False):

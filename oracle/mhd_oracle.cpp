@@ -295,6 +295,159 @@ S uct(const S SW[8], const S SE[8], const S NW[8], const S NE[8], int e,
   return avg - difa + difb;
 }
 
+/* Wave fan of the one-dimensional HLLD problem at a face (§2.1 "HLLD Solver", Fig. 1; Miyoshi
+ * & Kusano 2005), as the edge EMF below needs it: the five wave speeds, and per side the
+ * single-star density, its square root and the two factors of the single-star relations
+ * B*_t = B_t tb and u*_t = u_t - B_t tv, which hold for either transverse component (1 and 0
+ * where the star denominator degenerates, the switch of reading R6).  Each side is given as
+ * (rho, u_n, p, B_t1, B_t2) with the shared normal field bn.  The same formulas as in hlld(). */
+template <class S>
+struct Fan {
+  S bn, sgn, sl, sr, sm, ssl, ssr;
+  S un[2], rs[2], sq[2], tb[2], tv[2];
+};
+
+template <class S>
+Fan<S> hlld_fan(S bn, const S lo[5], const S hi[5], const mhd_oracle_params& P) {
+  const double gam = P.gamma;
+  Fan<S> f;
+  f.bn = bn;
+  const S* side[2] = {lo, hi};
+  S pt[2], cf[2];
+  for (int k = 0; k < 2; ++k) {
+    const S* q = side[k];
+    f.un[k] = q[1];
+    pt[k] = q[2] + 0.5 * (bn * bn + q[3] * q[3] + q[4] * q[4]);
+    cf[k] = cfast(q[0], q[2], bn, q[3], q[4], gam);
+  }
+  const S cmx = smax(cf[0], cf[1]);
+  f.sl = smin(lo[1], hi[1]) - cmx;
+  f.sr = smax(lo[1], hi[1]) + cmx;
+  const S sdl = f.sl - lo[1], sdr = f.sr - hi[1];
+  const S den = sdr * hi[0] - sdl * lo[0];
+  f.sm = (sdr * hi[0] * hi[1] - sdl * lo[0] * lo[1] - pt[1] + pt[0]) / den;
+  const S spd[2] = {f.sl, f.sr}, sd[2] = {sdl, sdr};
+  for (int k = 0; k < 2; ++k) {
+    const S r = side[k][0], u = side[k][1];
+    f.rs[k] = r * sd[k] / (spd[k] - f.sm);
+    const S dd = r * sd[k] * (spd[k] - f.sm) - bn * bn;
+    const S ref = r * sd[k] * sd[k] + bn * bn;
+    if (sabs(dd) > P.eps_deg * ref) {
+      f.tv[k] = bn * (f.sm - u) / dd;
+      f.tb[k] = (r * sd[k] * sd[k] - bn * bn) / dd;
+    } else {
+      f.tv[k] = S(0.0);
+      f.tb[k] = S(1.0);
+    }
+    f.sq[k] = ssqrt(f.rs[k]);
+  }
+  f.ssl = f.sm - sabs(bn) / f.sq[0];
+  f.ssr = f.sm + sabs(bn) / f.sq[1];
+  f.sgn = (bn < S(0.0)) ? S(-1.0) : S(1.0);
+  return f;
+}
+
+/* HLLD flux along the face normal of one transverse field component B_t, from the pair
+ * (u_t, B_t) of that component on each side: u_n B_t - B_n u_t in the outer regions; across
+ * each wave the flux jumps by the wave speed times the jump of B_t (F* = F + S (B*_t - B_t),
+ * F** = F* + S* (B**_t - B*_t)), with the single-star values of the fan's relations and the
+ * double-star field of Miyoshi & Kusano (both sides' star values weighted by the square
+ * roots of the star densities, plus the velocity jump).  Region order of hlld(). */
+template <class S>
+S hlld_bt_flux(const Fan<S>& f, S vl, S bl, S vr, S br) {
+  const S Fl = f.un[0] * bl - f.bn * vl;
+  const S Fr = f.un[1] * br - f.bn * vr;
+  const S bsl = bl * f.tb[0], bsr = br * f.tb[1];
+  const S vsl = vl - bl * f.tv[0], vsr = vr - br * f.tv[1];
+  const S bss = (f.sq[0] * bsr + f.sq[1] * bsl + f.sq[0] * f.sq[1] * (vsr - vsl) * f.sgn) /
+                (f.sq[0] + f.sq[1]);
+  const S Fsl = Fl + f.sl * (bsl - bl);
+  const S Fsr = Fr + f.sr * (bsr - br);
+  if (f.sl > S(0.0)) return Fl;
+  if (f.ssl >= S(0.0)) return Fsl;
+  if (f.sm >= S(0.0)) return Fsl + f.ssl * (bss - bsl);
+  if (f.ssr >= S(0.0)) return Fsr + f.ssr * (bss - bsr);
+  if (f.sr >= S(0.0)) return Fsr;
+  return Fr;
+}
+
+/* The transverse-field flux of a fan is linear in the four values (u_t, B_t) of the two
+ * sides (the fan's speeds and factors do not depend on them once the states are given), so
+ * it equals A_lo B_t,lo + A_hi B_t,hi + C_lo u_t,lo + C_hi u_t,hi.  The coefficients are
+ * read off by evaluating the flux on unit values.  The velocity coefficients carry the
+ * factor -B_n: w_k = -C_k / B_n are the weights with which the fan advects the transverse
+ * velocity (w_lo + w_hi = 1; for B_n = 0 the side of the contact: (1, 0) if S_M >= 0). */
+template <class S>
+void hlld_bt_coefs(const Fan<S>& f, S A[2], S w[2]) {
+  const S z = S(0.0), one = S(1.0);
+  A[0] = hlld_bt_flux(f, z, one, z, z);
+  A[1] = hlld_bt_flux(f, z, z, z, one);
+  if (sabs(f.bn) > S(0.0)) {
+    w[0] = -hlld_bt_flux(f, one, z, z, z) / f.bn;
+    w[1] = -hlld_bt_flux(f, z, z, one, z) / f.bn;
+  } else {
+    w[0] = (f.sm >= S(0.0)) ? one : z;
+    w[1] = one - w[0];
+  }
+}
+
+/* Edge EMF with the HLLD wave fan (UCT-HLLD, reading R21; §2.1 "Constrained transport and
+ * 2D-extension of the HLLD solver", Fig. 3).  The four corner states around an edge along e
+ * pose four one-dimensional HLLD problems: along a on the rows S (SW|SE) and N (NW|NE), whose
+ * normal field is that row's B_a, and along b on the columns W (SW|NW) and E (SE|NE), whose
+ * normal field is that column's B_b.  EMF_e = u_a B_b - u_b B_a is the a-flux of B_b and minus
+ * the b-flux of B_a.  The EMF takes the field part (the B_b terms) of the a-problems' fluxes
+ * and minus the field part (the B_a terms) of the b-problems' fluxes, the velocity part of
+ * each being carried by the other direction's problems:
+ *   - the velocity weights of the two rows (a-problems) averaged over the rows, and those of
+ *     the two columns averaged over the columns, give a first upwind weight per column and
+ *     per row;
+ *   - the rows' field parts are combined with the columns' velocity weights for those rows,
+ *     averaged over the columns with the first weights per column; the columns' field parts
+ *     likewise with the rows' velocity weights, averaged over the rows.
+ * With data that vary only along a this is exactly the HLLD a-flux of B_b (the b-problems
+ * then have equal sides, whose field coefficients add up to u_b, so their part becomes the
+ * a-problem's velocity terms), symmetrically along b; with flow supersonic along +a (or -a) it
+ * is exactly minus the HLLD b-flux of B_a of the column W (or E), symmetrically along b. */
+template <class S>
+S uct_hlld(const S SW[8], const S SE[8], const S NW[8], const S NE[8], int e,
+           const mhd_oracle_params& P) {
+  const int a = (e + 1) % 3, b = (e + 2) % 3;
+  // one-dimensional problem along n between corner states lo and hi: (rho, u_n, p, B_t1,
+  // B_t2) with (n, t1, t2) cyclic, normal field from lo (it is shared by the two sides)
+  auto coefs = [&](const S* lo, const S* hi, int n, S A[2], S w[2]) {
+    const int t1 = (n + 1) % 3, t2 = (n + 2) % 3;
+    const S ql[5] = {lo[0], lo[1 + n], lo[4], lo[5 + t1], lo[5 + t2]};
+    const S qh[5] = {hi[0], hi[1 + n], hi[4], hi[5 + t1], hi[5 + t2]};
+    hlld_bt_coefs(hlld_fan(lo[5 + n], ql, qh, P), A, w);
+  };
+  S Ar[2][2], wr[2][2], Ac[2][2], wc[2][2];  // [row S, N] along a; [column W, E] along b
+  coefs(SW, SE, a, Ar[0], wr[0]);
+  coefs(NW, NE, a, Ar[1], wr[1]);
+  coefs(SW, NW, b, Ac[0], wc[0]);
+  coefs(SE, NE, b, Ac[1], wc[1]);
+  // first upwind weights: per column from the rows, per row from the columns
+  S col1[2], row1[2];
+  for (int k = 0; k < 2; ++k) {
+    col1[k] = 0.5 * (wr[0][k] + wr[1][k]);
+    row1[k] = 0.5 * (wc[0][k] + wc[1][k]);
+  }
+  // weight of each row's field part (the columns' velocity weights for that row) and of each
+  // column's field part (the rows' velocity weights for that column)
+  S wrow[2], wcol[2];
+  for (int k = 0; k < 2; ++k) {
+    wrow[k] = col1[0] * wc[0][k] + col1[1] * wc[1][k];
+    wcol[k] = row1[0] * wr[0][k] + row1[1] * wr[1][k];
+  }
+  const S BbW = SW[5 + b], BbE = SE[5 + b], BaS = SW[5 + a], BaN = NW[5 + a];
+  S fa = S(0.0), fb = S(0.0);
+  for (int k = 0; k < 2; ++k) {
+    fa = fa + wrow[k] * (Ar[k][0] * BbW + Ar[k][1] * BbE);
+    fb = fb + wcol[k] * (Ac[k][0] * BaS + Ac[k][1] * BaN);
+  }
+  return fa - fb;
+}
+
 /* Time derivative of the primitive variables (rho, u, p, B) of ideal MHD, used for the
  * forward-Euler half-step of the MUSCL predictor (§2.1 "The MUSCL Scheme").  The
  * u(div B) term of the induction equation is dropped (div B = 0 form). */
@@ -596,7 +749,8 @@ struct Stepper {
         corner_state(c - ob, e, -1, +1, SE);
         corner_state(c - oa, e, +1, -1, NW);
         corner_state(c, e, -1, -1, NE);
-        emf[e][c] = uct(SW, SE, NW, NE, e, P);
+        emf[e][c] = P.emf_solver == 1 ? uct_hlld(SW, SE, NW, NE, e, P)
+                                       : uct(SW, SE, NW, NE, e, P);
       });
     }
   }
@@ -664,7 +818,8 @@ double cfl_patch(const Geom& G, const double* U, const double dx[3], const mhd_o
 
 bool check_params(const mhd_oracle_params* p) {
   return p && p->gamma > 1.0 && p->cfl > 0.0 && p->rho_floor > 0.0 && p->p_floor > 0.0 &&
-         p->eps_deg >= 0.0 && (p->limiter == 0 || p->limiter == 1);
+         p->eps_deg >= 0.0 && (p->limiter == 0 || p->limiter == 1) &&
+         (p->emf_solver == 0 || p->emf_solver == 1);
 }
 
 long patch_elems(const int32_t n[3], int g) {
@@ -777,6 +932,14 @@ int mhd_oracle_threads(void) {
   return omp_get_max_threads();
 #else
   return 1;
+#endif
+}
+
+void mhd_oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
 #endif
 }
 
@@ -965,7 +1128,8 @@ double mhd_oracle_cfast(double rho, double p, double bn, double bt1, double bt2,
 double mhd_oracle_limiter(double dl, double dr, int32_t lim) { return limiter(dl, dr, lim); }
 
 double mhd_oracle_uct(const double W[4][8], const mhd_oracle_params* prm) {
-  return uct(W[0], W[1], W[2], W[3], 2, *prm);
+  return prm->emf_solver == 1 ? uct_hlld(W[0], W[1], W[2], W[3], 2, *prm)
+                              : uct(W[0], W[1], W[2], W[3], 2, *prm);
 }
 
 void mhd_oracle_dqdt(const double q[8], const double D[3][8], const int32_t act[3], double gamma,

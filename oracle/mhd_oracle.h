@@ -29,10 +29,13 @@ typedef struct {
   double p_floor;    /* pressure floor applied to every reconstructed state */
   double eps_deg;    /* relative threshold of the HLLD degeneracy switch */
   int32_t limiter;   /* 0 = monotonised central (MC), 1 = minmod */
+  int32_t emf_solver; /* edge EMF: 0 = UCT-HLL, 1 = UCT-HLLD (four-state compositions) */
 } mhd_oracle_params;
 
 /* Threads the multi-patch entry points use (OpenMP over patches). */
 int mhd_oracle_threads(void);
+/* Sets the OpenMP thread count of the multi-patch entry points (n >= 1). */
+void mhd_oracle_set_threads(int n);
 
 /* One update of one patch: U_out interior <- U_in advanced by dt.  Guards of U_out are a
  * copy of U_in's.  nfloor (may be NULL) is int64_t[3] and accumulates floor activations
@@ -131,7 +134,7 @@ double mhd_oracle_cfast(double rho, double p, double bn, double bt1, double bt2,
 double mhd_oracle_limiter(double dl, double dr, int32_t limiter);
 
 /* Edge EMF (z component) from the four corner states around a z edge, each given as
- * (rho, u, v, w, p, Bx, By, Bz) in the order SW, SE, NW, NE. */
+ * (rho, u, v, w, p, Bx, By, Bz) in the order SW, SE, NW, NE; solver per prm->emf_solver. */
 double mhd_oracle_uct(const double W[4][8], const mhd_oracle_params* prm);
 
 /* Primitive-variable time derivative used by the half-step predictor.
