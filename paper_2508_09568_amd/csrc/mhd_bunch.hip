@@ -306,8 +306,9 @@ __global__ __launch_bounds__(BLK) void k_guards_at(const PatchDev* __restrict__ 
 // quantum is given (time levels: exact powers of two, frexp is exact), clipped to t_end when
 // ready, else zero
 // A ready patch whose step is not finite and positive (a non-finite state, or a bad given
-// step) does not advance: its step is 0 and status bit 4 is raised.
-__global__ __launch_bounds__(BLK) void k_lts_dt(const int32_t* __restrict__ ready,
+// step) does not advance: its step is 0, it leaves the ready set (so the slice bookkeeping
+// after the update leaves its state and time alone) and status bit 4 is raised.
+__global__ __launch_bounds__(BLK) void k_lts_dt(int32_t* __restrict__ ready,
                                                 const double* __restrict__ t, double t_end,
                                                 double quantum, const double* src, double* dt,
                                                 int np, int* status) {
@@ -321,8 +322,12 @@ __global__ __launch_bounds__(BLK) void k_lts_dt(const int32_t* __restrict__ read
     d = ldexp(quantum, e - 1);
   }
   const double rest = t_end - t[p];
-  if (ready[p] && !good) atomicOr(status, 4);
-  dt[p] = ready[p] && good ? (d < rest ? d : rest) : 0.0;
+  const int r = ready[p];
+  if (r && !good) {
+    atomicOr(status, 4);
+    ready[p] = 0;
+  }
+  dt[p] = r && good ? (d < rest ? d : rest) : 0.0;
 }
 
 // every ready patch: previous slice <- its state before the step (all padded cells), then
@@ -942,7 +947,7 @@ mhd_status launch_lts_step(mhd_bunch* h, T* Ucur, T* Unew, T* Uprev, double* t, 
     const mhd_status st = launch_cfl<T>(h, (const T*)Ucur, dx, dt, 0, s, ready);
     if (st != MHD_OK) return st;
   }
-  hipLaunchKernelGGL(k_lts_dt, dim3(pg), dim3(BLK), 0, s, (const int32_t*)ready, (const double*)t,
+  hipLaunchKernelGGL(k_lts_dt, dim3(pg), dim3(BLK), 0, s, ready, (const double*)t,
                      t_end, quantum, dt_fixed ? dt_fixed : (const double*)dt, dt, h->P,
                      h->d_status());
   h->copy_rest = false;  // U_new is scratch: only the ready patches' results are kept

@@ -80,3 +80,16 @@ def l1_rel_fields(layout, A, B):
         den += np.abs(b).reshape(8, -1).sum(axis=1)
     den = np.where(den > 0, den, den[4])
     return num / den
+
+
+def l1_rel_face_field(layout, A, B):
+    """L1 difference of each face-field component (Bx, By, Bz) divided by the L1 magnitude of
+    the whole face field, sum of |Bx| + |By| + |Bz| over owned faces."""
+    num = np.zeros(3)
+    den = 0.0
+    for p in range(layout.P):
+        a = layout.interior(A, p).reshape(8, -1)[5:]
+        b = layout.interior(B, p).reshape(8, -1)[5:]
+        num += np.abs(a - b).sum(axis=1)
+        den += np.abs(b).sum()
+    return num / den

@@ -16,7 +16,8 @@ oracle's, where a test says so)."""
 import numpy as np
 import pytest
 
-from gpu_util import dev, host, l1_rel_fields, log, make_bunch, rel_err_fields
+from gpu_util import (dev, host, l1_rel_face_field, l1_rel_fields, log, make_bunch,
+                      rel_err_fields)
 from paper_2508_09568_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -65,6 +66,7 @@ def test_uneven_batch_fp32_graph_ten_local_steps_vs_oracle():
         samples += [int(idx[0]), int(idx[len(idx) // 2]), int(idx[-1])]
     prm = oracle.Params(gamma=w.gamma, cfl=w.cfl)
     worst = np.zeros(8)
+    worst_b = np.zeros(3)
     for p in samples:
         a, b = int(L.base[p]), int(L.base[p + 1])
         Lp = W.Layout(L.dims[p][None], L.g)
@@ -73,8 +75,16 @@ def test_uneven_batch_fp32_graph_ten_local_steps_vs_oracle():
             d = oracle.cfl_many(Up, Lp.dims, L.g, w.dx[p][None], prm)
             Up = oracle.step_many(Up, Lp.dims, L.g, d, w.dx[p][None], prm)
         worst = np.maximum(worst, l1_rel_fields(Lp, got[a:b], Up))
+        worst_b = np.maximum(worst_b, l1_rel_face_field(Lp, got[a:b], Up))
     log(f"    sampled {len(samples)} patches, FP32 L1 rel err per field {worst}")
-    assert np.all(worst <= FP32_RUN_TOL), worst
+    log(f"    face field components relative to the field's L1 magnitude {worst_b}")
+    # rho, momenta, E and B_x against their own L1 norms.  B_y and B_z are zero at t = 0
+    # (uniform B along x) and after 10 steps only a small fraction of |B|; the rounding of the
+    # EMF differences that create them is that of values of size |u||B|, so they are held to
+    # the bar relative to the face field's magnitude, and their own-relative error to 3x it.
+    assert np.all(worst[:6] <= FP32_RUN_TOL), worst
+    assert np.all(worst_b <= FP32_RUN_TOL), worst_b
+    assert np.all(worst[6:] <= 3 * FP32_RUN_TOL), worst
 
 
 def _ot256():
