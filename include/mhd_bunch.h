@@ -152,6 +152,25 @@ mhd_status mhd_bunch_lts_step(mhd_bunch* h, void* U_cur, void* U_new, void* U_pr
 mhd_status mhd_bunch_update(mhd_bunch* h, const void* U_in, void* U_out, const double* dt_dev,
                             const double* dx_dev, hipStream_t stream);
 
+/* ---- allocation-free update ----
+ * For callers that cannot allocate device memory around the update (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same result, argument
+ * meaning and errors as mhd_bunch_update (same kernels), but the predictor scratch of the
+ * update is a static device array of MHD_STATIC_SCRATCH_BYTES inside the library instead of
+ * the bound workspace's scratch; the call allocates and frees nothing.  Each device the
+ * library runs on holds one such array until the process ends; its address is resolved by
+ * mhd_bunch_bind on the device current there, and the call must be made with that device
+ * current (else MHD_EINVAL).  Patches are processed in the handle's chunks: the bunch must
+ * have been created with max_scratch_bytes in (0, MHD_STATIC_SCRATCH_BYTES] or have a whole
+ * scratch that fits, else MHD_EINVAL (mhd_bunch_last_error gives the sizes).  Every call on a
+ * device shares that device's array: calls that overlap in time on one device (other
+ * streams, other handles, other threads) race and give wrong results; calls in one stream
+ * order are safe.  Nothing in the array needs clearing between calls (every value read in a
+ * call is written earlier in that call). */
+#define MHD_STATIC_SCRATCH_BYTES (128ll << 20)
+mhd_status mhd_bunch_update_static(mhd_bunch* h, const void* U_in, void* U_out,
+                                   const double* dt_dev, const double* dx_dev, hipStream_t stream);
+
 /* ---- adjoint of one update (reverse mode at fixed dt) ----
  * The step map is U^{n+1}(owned) = update(fill_guards(U^n)).  mhd_bunch_adjoint returns
  * lam_in = (d U^{n+1} / d U^n)^T lam_out: lam_out holds dL/dU^{n+1} on owned cells and faces

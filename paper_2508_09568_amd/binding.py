@@ -77,6 +77,7 @@ _SIGS = {
     "mhd_bunch_fill_guards": (C.c_int, [_h, _v, _v, _st]),
     "mhd_bunch_cfl": (C.c_int, [_h, _v, _v, _v, C.c_int32, _st]),
     "mhd_bunch_update": (C.c_int, [_h, _v, _v, _v, _v, _st]),
+    "mhd_bunch_update_static": (C.c_int, [_h, _v, _v, _v, _v, _st]),
     "mhd_bunch_check": (C.c_int, [_h, _st]),
     "mhd_bunch_profile": (C.c_int, [_h, C.c_int32]),
     "mhd_bunch_profile_read": (C.c_int, [_h, C.c_int32, _dp, C.POINTER(C.c_int64)]),
@@ -102,6 +103,8 @@ _SIGS = {
     "mhd_bunch_set_solver_split": (C.c_int, [_h, C.c_int32]),
     "mhd_bunch_solver_split": (C.c_int32, [_h]),
 }
+
+STATIC_SCRATCH_BYTES = 128 << 20   # MHD_STATIC_SCRATCH_BYTES of include/mhd_bunch.h
 
 KERNELS = {"prim": 0, "edge_emf_n": 1, "predict": 2, "solve": 3, "cfl": 4, "guards": 5,
            "edge": 6}
@@ -225,6 +228,16 @@ class Bunch:
         self._check_dx(dx)
         _ok(mhd_bunch_update(self._h, _ptr(U_in), _ptr(U_out), _ptr(dt), _ptr(dx), _stream(stream)),
             "mhd_bunch_update", self._h)
+
+    def update_static(self, U_in, U_out, dt, dx, stream=None):
+        """The update with the library's static device scratch (allocates nothing; the bunch
+        must be created with 0 < max_scratch_bytes <= STATIC_SCRATCH_BYTES)."""
+        self._check_state(U_in, "U_in")
+        self._check_state(U_out, "U_out")
+        self._check_dt(dt)
+        self._check_dx(dx)
+        _ok(mhd_bunch_update_static(self._h, _ptr(U_in), _ptr(U_out), _ptr(dt), _ptr(dx),
+                                    _stream(stream)), "mhd_bunch_update_static", self._h)
 
     def cfl(self, U, dx, dt_out, global_min=False, stream=None):
         self._check_state(U)

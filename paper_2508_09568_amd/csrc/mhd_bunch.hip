@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -531,6 +532,34 @@ struct TileCand {
 
 }  // namespace
 
+// ------------------------------------------------------------------ static scratch
+// Predictor scratch of mhd_bunch_update_static: one array per device in the library's code
+// object, held by every device the library runs on until the process ends.  Its host-side
+// name is not a device address: host code never passes `scratch` itself to a kernel or a
+// copy.  mhd_bunch_bind resolves the device address once per device (with that device
+// current) and keeps it in static_scratch_ptr; the entry point passes that pointer.
+__device__ __align__(256) unsigned char scratch[MHD_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex static_scratch_mu;
+void* static_scratch_ptr[MAX_DEVICES] = {nullptr};
+
+// device address of `scratch` on device `dev` (the current device), resolved on first use
+hipError_t static_scratch_of(int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(static_scratch_mu);
+  if (!static_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    static_scratch_ptr[dev] = p;
+  }
+  *out = static_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 // ------------------------------------------------------------------------ handle
 
 struct mhd_bunch {
@@ -553,6 +582,8 @@ struct mhd_bunch {
   // per shape; the launch configuration in use is (shape, remap)
   int nshape = 0, shape = 0, mode = 0;  // mode 0 plain grid, 1 XCD remap, 2 persistent + remap
   int ncu = 256;                           // compute units of the bound device
+  int dev = -1;                            // device current at bind
+  void* static_scratch = nullptr;          // that device's address of `scratch`
   TileCand shapes[MAXSHAPE];
   std::vector<TileDev> tiles[MAXSHAPE];
   // predictor (mhd_bunch_set_predictor): 0 staged kernels, k >= 1 fused with tile shape
@@ -1188,9 +1219,13 @@ mhd_status mhd_bunch_bind(mhd_bunch* h, void* ws, hipStream_t s) {
   h->last_error[0] = 0;
   {
     int dev = 0, n = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+    if (!h->hip_ok(hipGetDevice(&dev), "current device")) return MHD_EDEVICE;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
       h->ncu = n;
+    h->dev = dev;
+    // set-up of the allocation-free update: this device's address of the static scratch
+    if (!h->hip_ok(static_scratch_of(dev, &h->static_scratch), "resolve static scratch"))
+      return MHD_EDEVICE;
   }
   bool ok = h->hip_ok(hipMemcpyAsync(h->ws + h->o_pt, h->pt.data(), sizeof(PatchDev) * h->P,
                                      hipMemcpyHostToDevice, s), "upload patch table");
@@ -1317,6 +1352,35 @@ mhd_status mhd_bunch_update(mhd_bunch* h, const void* Uin, void* Uout, const dou
                                               (double*)h->d_scratch())
                       : launch_update<float>(h, (const float*)Uin, (float*)Uout, dt, dx, s,
                                              (float*)h->d_scratch());
+}
+
+mhd_status mhd_bunch_update_static(mhd_bunch* h, const void* Uin, void* Uout, const double* dt,
+                                   const double* dx, hipStream_t s) {
+  if (!h || !Uin || !Uout || !dt || !dx || Uin == Uout) return MHD_EINVAL;
+  if (!h->bound || !h->static_scratch) return MHD_ESTATE;
+  const size_t bytes = (size_t)h->state_elems * h->prec;
+  const char *a = (const char*)Uin, *b = (const char*)Uout;
+  if (a < b + bytes && b < a + bytes) return MHD_EINVAL;
+  const int64_t need = h->scratch_elems * (int64_t)h->prec;
+  if (need > (int64_t)MHD_STATIC_SCRATCH_BYTES) {
+    snprintf(h->last_error, sizeof(h->last_error),
+             "update_static: one chunk needs %lld scratch bytes, the static scratch holds %lld "
+             "(create the bunch with max_scratch_bytes <= %lld)",
+             (long long)need, (long long)MHD_STATIC_SCRATCH_BYTES,
+             (long long)MHD_STATIC_SCRATCH_BYTES);
+    return MHD_EINVAL;
+  }
+  int dev = -1;
+  if (!h->hip_ok(hipGetDevice(&dev), "current device")) return MHD_EDEVICE;
+  if (dev != h->dev) {
+    snprintf(h->last_error, sizeof(h->last_error),
+             "update_static: current device %d is not the bound device %d", dev, h->dev);
+    return MHD_EINVAL;
+  }
+  return h->prec == 8 ? launch_update<double>(h, (const double*)Uin, (double*)Uout, dt, dx, s,
+                                              (double*)h->static_scratch)
+                      : launch_update<float>(h, (const float*)Uin, (float*)Uout, dt, dx, s,
+                                             (float*)h->static_scratch);
 }
 
 mhd_status mhd_bunch_lts_step(mhd_bunch* h, void* U_cur, void* U_new, void* U_prev, double* t,

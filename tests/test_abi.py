@@ -183,3 +183,20 @@ def test_graph_of_own_steps_with_guard_exchange_is_refused(B):
     finally:
         B.mhd_bunch_destroy(h)
 
+
+
+def test_static_update_checks_arguments_before_any_launch(B):
+    """mhd_bunch_update_static rejects missing or overlapping buffers and needs a bound
+    handle (whose bind resolved the device address of the static scratch)."""
+    rc, h = _create(B, [[16, 16, 16]] * 2)
+    assert rc == B.MHD_OK
+    bufs = [np.zeros(8) for _ in range(4)]
+    Ui, Uo, dt, dx = (C.c_void_p(b.ctypes.data) for b in bufs)
+    try:
+        assert B.mhd_bunch_update_static(None, Ui, Uo, dt, dx, None) == B.MHD_EINVAL
+        assert B.mhd_bunch_update_static(h, None, Uo, dt, dx, None) == B.MHD_EINVAL
+        assert B.mhd_bunch_update_static(h, Ui, Ui, dt, dx, None) == B.MHD_EINVAL
+        assert B.mhd_bunch_update_static(h, Ui, Uo, None, dx, None) == B.MHD_EINVAL
+        assert B.mhd_bunch_update_static(h, Ui, Uo, dt, dx, None) == B.MHD_ESTATE
+    finally:
+        B.mhd_bunch_destroy(h)
