@@ -67,6 +67,13 @@ typedef struct {
   double eps_deg;         /* relative threshold of the HLLD degeneracy switch */
   int64_t max_scratch_bytes; /* cap of the per-call scratch (patches are processed in
                                 chunks that fit); 0 = no cap */
+  int32_t emf_solver;     /* edge EMF from the four predicted corner states (§2.1 "Constrained
+                             transport and 2D-extension of the HLLD solver", Fig. 3):
+                             0 = UCT-HLL (two composed one-dimensional HLL fluxes, outer
+                             speeds bounded over the four states);
+                             1 = UCT-HLLD (the four one-dimensional HLLD problems of the rows
+                             and columns; reduces to the HLLD flux of the transverse field
+                             for data varying along one direction) */
 } mhd_bunch_desc;
 
 /* Validates the description and builds the host-side patch and launch tables.  No

@@ -55,6 +55,7 @@ class mhd_bunch_desc(C.Structure):
         ("p_floor", C.c_double),
         ("eps_deg", C.c_double),
         ("max_scratch_bytes", C.c_int64),
+        ("emf_solver", C.c_int32),
     ]
 
 
@@ -155,12 +156,13 @@ class Bunch:
 
     def __init__(self, dims, g=3, precision=8, gamma=5.0 / 3.0, cfl=0.4, limiter=0,
                  rho_floor=1e-12, p_floor=1e-12, eps_deg=1e-10, max_scratch_bytes=0,
-                 device="cuda", stream=None):
+                 emf_solver=0, device="cuda", stream=None):
         import numpy as np
         import torch
         self._dims = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
         d = mhd_bunch_desc(self._dims.shape[0], self._dims.ctypes.data_as(_ip), g, precision,
-                           gamma, cfl, limiter, rho_floor, p_floor, eps_deg, max_scratch_bytes)
+                           gamma, cfl, limiter, rho_floor, p_floor, eps_deg, max_scratch_bytes,
+                           emf_solver)
         h = _h()
         _ok(mhd_bunch_create(C.byref(h), C.byref(d)), "mhd_bunch_create")
         self._h = h
@@ -386,3 +388,4 @@ class Bunch:
 
     def graph_launch(self, stream=None):
         _ok(mhd_bunch_graph_launch(self._h, _stream(stream)), "mhd_bunch_graph_launch", self._h)
+

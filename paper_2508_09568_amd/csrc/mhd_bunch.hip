@@ -136,7 +136,7 @@ struct SolveWaves {
   static constexpr int RAW = BY_LDS < CAP ? BY_LDS : CAP;
   static constexpr int value = RAW / PER * PER < 1 ? 1 : RAW / PER * PER;
 };
-template <typename T, int TX, int TY, int TZ, int FORM>
+template <typename T, int TX, int TY, int TZ, int FORM, int EMF>
 __global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS))
 __attribute__((amdgpu_waves_per_eu(SolveWaves<T, TX, TY, TZ, FORM>::value))) void k_solve(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, const T* __restrict__ Uin,
@@ -151,7 +151,7 @@ __attribute__((amdgpu_waves_per_eu(SolveWaves<T, TX, TY, TZ, FORM>::value))) voi
       if (copy_rest) copy_tile<TX, TY, TZ>(ex, P, g, tl, Uin, Uout);
       continue;
     }
-    solve_tile<T, TX, TY, TZ, FORM>(ex, lds, P, g, tl, Uin, Uout, S, dt[tl.patch],
+    solve_tile<T, TX, TY, TZ, FORM, EMF>(ex, lds, P, g, tl, Uin, Uout, S, dt[tl.patch],
                                     dx + 3 * tl.patch, c);
     ex.sync();  // the next tile reuses the shared memory
   }
@@ -188,7 +188,7 @@ __attribute__((amdgpu_waves_per_eu(PredWaves<T, PX, PY, PZ>::value))) void k_pre
 
 // half-step edge EMFs, each edge once, by the solver tiles that own them (solver form 2); no
 // shared memory: registers alone set the occupancy, three waves per SIMD (<= 168 VGPRs)
-template <typename T, int TX, int TY, int TZ>
+template <typename T, int TX, int TY, int TZ, int EMF>
 __global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS)) __attribute__((amdgpu_waves_per_eu(3)))
 void k_edges(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, T* __restrict__ S,
@@ -199,7 +199,7 @@ void k_edges(
     const TileDev tl = tiles[logical_block(vb, ntile, remap)];
     if (dt[tl.patch] == 0.0) continue;  // patch at rest: no EMFs needed
     const PatchDev& P = pt[tl.patch];
-    solve_tile<T, TX, TY, TZ, 3>(ex, (T*)nullptr, P, g, tl, (const T*)S, S, S, 1.0, dx + 3 * tl.patch,
+    solve_tile<T, TX, TY, TZ, 3, EMF>(ex, (T*)nullptr, P, g, tl, (const T*)S, S, S, 1.0, dx + 3 * tl.patch,
                                  c);
   }
 }
@@ -563,7 +563,7 @@ hipError_t static_scratch_of(int dev, void** out) {
 // ------------------------------------------------------------------------ handle
 
 struct mhd_bunch {
-  int P = 0, g = 3, prec = 8, limiter = 0;
+  int P = 0, g = 3, prec = 8, limiter = 0, emf = 0;
   double gamma = 5.0 / 3.0, cfl = 0.4, rho_floor = 1e-12, p_floor = 1e-12, eps_deg = 1e-10;
   int64_t max_scratch = 0;
   std::vector<PatchDev> pt;
@@ -668,6 +668,7 @@ struct mhd_bunch {
     c.eps_deg = T(eps_deg);
     c.tiny = sizeof(T) == 8 ? T(1e-300) : T(1e-37);
     c.limiter = limiter;
+    c.emf = emf;
     return c;
   }
   // persistent grid: at most `per_cu` work-groups per compute unit, a multiple of the XCD
@@ -712,36 +713,36 @@ void set_shapes(mhd_bunch* h) {
 #undef MHD_ADD
 }
 
-template <typename T, int X, int Y, int Z, int FORM>
+template <typename T, int X, int Y, int Z, int FORM, int EMF>
 void solve_launch(mhd_bunch* h, int nt, const TileDev* tl, const T* Uin, T* Uout, const T* S,
                   const double* dt, const double* dx, const Consts<T>& c, hipStream_t s) {
   int grid = nt;
   if (h->mode == 2) {
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void*>(k_solve<T, X, Y, Z, FORM>),
+            &occ, reinterpret_cast<const void*>(k_solve<T, X, Y, Z, FORM, EMF>),
             TileShape<X, Y, Z>::THREADS, 0) != hipSuccess || occ < 1)
       occ = 1;
     grid = h->persistent_grid(nt, occ);
   }
-  hipLaunchKernelGGL((k_solve<T, X, Y, Z, FORM>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0,
+  hipLaunchKernelGGL((k_solve<T, X, Y, Z, FORM, EMF>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0,
                      s, h->d_pt(), tl, Uin, Uout, S, dt, dx, c, h->g, nt, h->mode >= 1,
                      h->copy_rest ? 1 : 0);
 }
 
-template <typename T, int X, int Y, int Z>
+template <typename T, int X, int Y, int Z, int EMF>
 void edges_launch(mhd_bunch* h, int nt, const TileDev* tl, T* S, const double* dt,
                   const double* dx, const Consts<T>& c, hipStream_t s) {
   int grid = nt;
   if (h->mode == 2) {
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void*>(k_edges<T, X, Y, Z>), TileShape<X, Y, Z>::THREADS,
+            &occ, reinterpret_cast<const void*>(k_edges<T, X, Y, Z, EMF>), TileShape<X, Y, Z>::THREADS,
             0) != hipSuccess || occ < 1)
       occ = 1;
     grid = h->persistent_grid(nt, occ);
   }
-  hipLaunchKernelGGL((k_edges<T, X, Y, Z>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0, s,
+  hipLaunchKernelGGL((k_edges<T, X, Y, Z, EMF>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0, s,
                      h->d_pt(), tl, S, dt, dx, c, h->g, nt, h->mode >= 1);
 }
 
@@ -754,16 +755,22 @@ void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uou
   const TileCand tc = h->shapes[k];
   const int nt = ch.ntile[k];
   const TileDev* tl = h->d_tiles(k) + ch.tile0[k];
+#define MHD_TRY_EMF(X, Y, Z, EMF)                                                             \
+  if (edges)                                                                                  \
+    edges_launch<T, X, Y, Z, EMF>(h, nt, tl, S, dt, dx, c, s);                                \
+  else if (h->split == 2)                                                                     \
+    solve_launch<T, X, Y, Z, 2, EMF>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                  \
+  else if (h->split == 1)                                                                     \
+    solve_launch<T, X, Y, Z, 1, EMF>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                  \
+  else                                                                                        \
+    solve_launch<T, X, Y, Z, 0, EMF>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);
 #define MHD_TRY(X, Y, Z)                                                                      \
   if (tc.x == X && tc.y == Y && tc.z == Z) {                                                  \
-    if (edges)                                                                                \
-      edges_launch<T, X, Y, Z>(h, nt, tl, S, dt, dx, c, s);                                       \
-    else if (h->split == 2)                                                                   \
-      solve_launch<T, X, Y, Z, 2>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                    \
-    else if (h->split == 1)                                                                   \
-      solve_launch<T, X, Y, Z, 1>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                    \
-    else                                                                                      \
-      solve_launch<T, X, Y, Z, 0>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                    \
+    if (h->emf == 1) {                                                                        \
+      MHD_TRY_EMF(X, Y, Z, 1)                                                                 \
+    } else {                                                                                  \
+      MHD_TRY_EMF(X, Y, Z, 0)                                                                 \
+    }                                                                                         \
     return;                                                                                   \
   }
   switch (h->act) {
@@ -776,6 +783,7 @@ void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uou
     default: MHD_SHAPES_4(MHD_TRY) break;
   }
 #undef MHD_TRY
+#undef MHD_TRY_EMF
 }
 
 // S: scratch of one chunk of patches
@@ -1041,7 +1049,8 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
   if (!out || !d || !d->dims || d->n_patches < 1) return MHD_EINVAL;
   if (d->guard < 3 || (d->precision != 4 && d->precision != 8)) return MHD_EINVAL;
   if (!(d->gamma > 1.0) || !(d->cfl > 0.0) || !(d->rho_floor > 0.0) || !(d->p_floor > 0.0) ||
-      !(d->eps_deg >= 0.0) || (d->limiter != 0 && d->limiter != 1) || d->max_scratch_bytes < 0)
+      !(d->eps_deg >= 0.0) || (d->limiter != 0 && d->limiter != 1) || d->max_scratch_bytes < 0 ||
+      (d->emf_solver != 0 && d->emf_solver != 1))
     return MHD_EINVAL;
   mhd_bunch* h = new (std::nothrow) mhd_bunch;
   if (!h) return MHD_ENOMEM;
@@ -1051,6 +1060,7 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
   h->gamma = d->gamma;
   h->cfl = d->cfl;
   h->limiter = d->limiter;
+  h->emf = d->emf_solver;
   h->rho_floor = d->rho_floor;
   h->p_floor = d->p_floor;
   h->eps_deg = d->eps_deg;

@@ -166,6 +166,8 @@ struct Consts {
   T eps_deg;    // relative threshold of the HLLD degeneracy switch
   T tiny;       // guard of the EMF denominators
   int limiter;  // 0 monotonised central, 1 minmod
+  int emf;      // edge EMF: 0 UCT-HLL, 1 UCT-HLLD (kernels take it as a template parameter;
+                // the adjoint's dual-number gather reads it here)
 };
 
 // constants of one scalar type converted to another (e.g. T -> Dual<T>)
@@ -180,6 +182,7 @@ __host__ __device__ __forceinline__ Consts<S> lift(const Consts<T>& c) {
   o.eps_deg = S(c.eps_deg);
   o.tiny = S(c.tiny);
   o.limiter = c.limiter;
+  o.emf = c.emf;
   return o;
 }
 
@@ -406,6 +409,139 @@ __host__ __device__ __forceinline__ T uct_emf(const T C[4][7], const Consts<T>& 
   #pragma unroll
   for (int k = 0; k < 4; ++k) u.add(k, C[k], c);
   return u.finish(c);
+}
+
+
+// ---------------------------------------------------------------- UCT-HLLD edge EMF
+// The HLLD flux of one transverse field component B_t through a face, for given outer
+// states, is linear in that component's pair (u_t, B_t) on the two sides: the wave fan (its
+// speeds, single-star densities and the star relations B*_t = phi B_t, u*_t = u_t - kap B_t)
+// depends on the states but not on which transverse component is followed.  Written as
+//   F_t = A_lo B_t,lo + A_hi B_t,hi - B_n (w_lo u_t,lo + w_hi u_t,hi),  w_lo + w_hi = 1,
+// the coefficients are, region by region of the fan (S_L < S*_L < S_M < S*_R < S_R), with
+// r = sqrt(rho*) per side, q = 1 / (r_lo + r_hi), sg = sign(B_n):
+//   left of S_L:   A = (u_lo, 0),                      w = (1, 0)
+//   S_L..S*_L:     A = (u_lo + S_L (phi_lo - 1), 0),   w = (1, 0)
+//   S*_L..S_M:     A_lo = u_lo + S_L (phi_lo - 1) + S*_L ((r_hi phi_lo + r_lo r_hi sg kap_lo) q - phi_lo)
+//                  A_hi = S*_L (r_lo phi_hi - r_lo r_hi sg kap_hi) q,  w_hi = -S*_L r_lo r_hi q / |B_n|
+// and mirrored right of the contact (the jump of the flux across a wave is the wave speed times
+// the jump of B_t; the double-star field is Miyoshi & Kusano's r-weighted average of the two
+// single-star fields plus sg r_lo r_hi q times the velocity jump).  In the double-star regions
+// |B_n| > 0 (S*_L < 0 <= S_M needs |B_n| / r_lo > S_M >= 0), so the division is safe.
+template <typename T>
+struct BtCoef {
+  T A0, A1, w0, w1;
+};
+// lo, hi: (rho, u_n, p, B_t1, B_t2); bn: the shared normal field
+template <typename T>
+__host__ __device__ __forceinline__ BtCoef<T> hlld_bt_coef(const T lo[5], const T hi[5], T bn,
+                                                           const Consts<T>& c) {
+  const T bn2 = bn * bn;
+  const T* sd_[2] = {lo, hi};
+  T pt[2], cf[2];
+  #pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const T* q = sd_[k];
+    const T bt = q[3] * q[3] + q[4] * q[4];
+    pt[k] = q[2] + T(0.5) * (bn2 + bt);
+    cf[k] = fast_speed_t(wave_base(q[0], q[2], bn2 + bt, c.gamma), bt);
+  }
+  const T cmx = m_max(cf[0], cf[1]);
+  const T S0 = m_min(lo[1], hi[1]) - cmx, S1 = m_max(lo[1], hi[1]) + cmx;
+  const T mf0 = (S0 - lo[1]) * lo[0], mf1 = (S1 - hi[1]) * hi[0];  // rho (S - u) per side
+  const T sm = (mf1 * hi[1] - mf0 * lo[1] - pt[1] + pt[0]) * m_rcp(mf1 - mf0);
+  // star relations per side
+  T phi[2], kap[2], rs[2];
+  #pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const T Sk = k ? S1 : S0, mfk = k ? mf1 : mf0, uk = sd_[k][1];
+    const T sdk = Sk - uk;
+    rs[k] = mfk * m_rcp(Sk - sm);
+    const T dd = mfk * (Sk - sm) - bn2;
+    if (m_abs(dd) > c.eps_deg * (mfk * sdk + bn2)) {
+      const T idd = m_rcp(dd);
+      phi[k] = (mfk * sdk - bn2) * idd;
+      kap[k] = bn * (sm - uk) * idd;
+    } else {
+      phi[k] = T(1);
+      kap[k] = T(0);
+    }
+  }
+  const T isq0 = m_rsqrt(rs[0]), isq1 = m_rsqrt(rs[1]);
+  const T abn = m_abs(bn);
+  const T Ss0 = sm - abn * isq0, Ss1 = sm + abn * isq1;
+  // region of the face, in the order of the face solver (first test that holds)
+  const int reg = S0 > T(0) ? 0 : Ss0 >= T(0) ? 1 : sm >= T(0) ? 2 : Ss1 >= T(0) ? 3
+                : S1 >= T(0) ? 4 : 5;
+  BtCoef<T> o;
+  if (reg == 0) {
+    o.A0 = lo[1]; o.A1 = T(0); o.w0 = T(1); o.w1 = T(0);
+  } else if (reg == 1) {
+    o.A0 = lo[1] + S0 * (phi[0] - T(1)); o.A1 = T(0); o.w0 = T(1); o.w1 = T(0);
+  } else if (reg == 5) {
+    o.A0 = T(0); o.A1 = hi[1]; o.w0 = T(0); o.w1 = T(1);
+  } else if (reg == 4) {
+    o.A0 = T(0); o.A1 = hi[1] + S1 * (phi[1] - T(1)); o.w0 = T(0); o.w1 = T(1);
+  } else {
+    // double-star regions: r_lo r_hi q = 1 / (1/r_lo + 1/r_hi)
+    const T rq = m_rcp(isq0 + isq1);
+    const T sg = bn < T(0) ? T(-1) : T(1);
+    const T cl = isq0 * rq, ch = isq1 * rq;           // r_hi q and r_lo q
+    const T Blo = phi[0] * cl + sg * rq * kap[0];      // d B** / d B_lo
+    const T Bhi = phi[1] * ch - sg * rq * kap[1];      // d B** / d B_hi
+    const T wv = rq * m_rcp(abn);                      // r_lo r_hi q / |B_n|
+    if (reg == 2) {
+      o.A0 = lo[1] + S0 * (phi[0] - T(1)) + Ss0 * (Blo - phi[0]);
+      o.A1 = Ss0 * Bhi;
+      o.w1 = -Ss0 * wv;
+      o.w0 = T(1) - o.w1;
+    } else {
+      o.A1 = hi[1] + S1 * (phi[1] - T(1)) + Ss1 * (Bhi - phi[1]);
+      o.A0 = Ss1 * Blo;
+      o.w0 = Ss1 * wv;
+      o.w1 = T(1) - o.w0;
+    }
+  }
+  return o;
+}
+
+// Edge EMF from the four corner states (same layout and corner order as UctAcc: 0 SW, 1 SE,
+// 2 NW, 3 NE; C = (rho, u_a, u_b, p, B_e, B_a, B_b)) with the HLLD fan (the UCT-HLLD
+// composition).  Four one-dimensional problems: along a on the rows SW|SE and NW|NE (normal
+// field B_a of the row, transverse pair (B_b, B_e)), along b on the columns SW|NW and SE|NE
+// (normal field B_b of the column, transverse pair (B_e, B_a)).  EMF_e = u_a B_b - u_b B_a is
+// assembled from the B_b parts of the rows and minus the B_a parts of the columns; the row
+// parts are weighted by the columns' velocity weights, taken per column with the rows'
+// upwind weight of that column, and the column parts symmetrically.  Data varying along one
+// direction only give that direction's one-dimensional HLLD flux.
+template <typename T>
+__host__ __device__ __forceinline__ T uct_hlld_emf(const T C[4][7], const Consts<T>& c) {
+  BtCoef<T> row[2], col[2];
+  #pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const T* l = C[2 * k];
+    const T* h = C[2 * k + 1];
+    const T ql[5] = {l[0], l[1], l[3], l[6], l[4]};
+    const T qh[5] = {h[0], h[1], h[3], h[6], h[4]};
+    row[k] = hlld_bt_coef(ql, qh, l[5], c);
+  }
+  #pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const T* l = C[k];
+    const T* h = C[k + 2];
+    const T ql[5] = {l[0], l[2], l[3], l[4], l[5]};
+    const T qh[5] = {h[0], h[2], h[3], h[4], h[5]};
+    col[k] = hlld_bt_coef(ql, qh, l[6], c);
+  }
+  // rows' upwind weight of each column, columns' upwind weight of each row
+  const T cw0 = T(0.5) * (row[0].w0 + row[1].w0), cw1 = T(0.5) * (row[0].w1 + row[1].w1);
+  const T rw0 = T(0.5) * (col[0].w0 + col[1].w0), rw1 = T(0.5) * (col[0].w1 + col[1].w1);
+  const T wS = cw0 * col[0].w0 + cw1 * col[1].w0, wN = cw0 * col[0].w1 + cw1 * col[1].w1;
+  const T wW = rw0 * row[0].w0 + rw1 * row[1].w0, wE = rw0 * row[0].w1 + rw1 * row[1].w1;
+  const T BbW = C[0][6], BbE = C[1][6], BaS = C[0][5], BaN = C[2][5];
+  const T fa = wS * (row[0].A0 * BbW + row[0].A1 * BbE) + wN * (row[1].A0 * BbW + row[1].A1 * BbE);
+  const T fb = wW * (col[0].A0 * BaS + col[0].A1 * BaN) + wE * (col[1].A0 * BaS + col[1].A1 * BaN);
+  return fa - fb;
 }
 
 }  // namespace mhd

@@ -386,8 +386,9 @@ __host__ __device__ __forceinline__ void corner_state(const PatchDev& P, const A
 }
 
 // -------------------------------------------------------- stage 4b: edge EMF
-// Edge along e at the (a, b) = (-1/2, -1/2) corner of padded cell (i, j, k).
-template <typename S, class AW>
+// Edge along e at the (a, b) = (-1/2, -1/2) corner of padded cell (i, j, k).  EMF: 0 the
+// UCT-HLL composition, 1 UCT-HLLD.
+template <int EMF, typename S, class AW>
 __host__ __device__ __forceinline__ S edge_point(const PatchDev& P, int g, int e, int i, int j, int k,
                                                  const AW& w, const Consts<S>& c) {
   const int a = (e + 1) % 3, b = (e + 2) % 3;
@@ -398,7 +399,10 @@ __host__ __device__ __forceinline__ S edge_point(const PatchDev& P, int g, int e
   corner_state(P, w, wc - ob, e, -1, +1, c, C[1]);       // SE
   corner_state(P, w, wc - oa, e, +1, -1, c, C[2]);       // NW
   corner_state(P, w, wc, e, -1, -1, c, C[3]);            // NE
-  return uct_emf(C, c);
+  if constexpr (EMF == 1)
+    return uct_hlld_emf(C, c);
+  else
+    return uct_emf(C, c);
 }
 
 // Scheduling fence (device code): instructions are not moved across it, which bounds how many
@@ -458,7 +462,7 @@ __host__ __device__ __forceinline__ void face_x_point(const PatchDev& P, int g, 
   hlld_flux(s, w(wl + 1u + W_BH * Nw), c, F);
 }
 
-template <int E, typename S, class AW>
+template <int E, int EMF, typename S, class AW>
 __host__ __device__ __forceinline__ S edge_px_point(const PatchDev& P, int g, int i, int j, int k,
                                                     const AW& w, const Consts<S>& c) {
   static_assert(E == 1 || E == 2, "edges along y or z");
@@ -469,6 +473,7 @@ __host__ __device__ __forceinline__ S edge_px_point(const PatchDev& P, int g, in
   constexpr int t = E == 2 ? b : a;  // E = z: (a, b) = (x, y); E = y: (a, b) = (z, x)
   const uint32_t ot = (uint32_t)P.woff[t];
   UctAcc<S> u;
+  S Call[EMF == 1 ? 4 : 1][7];  // UCT-HLLD: all four corners at once
   #pragma unroll
   for (int row = 0; row < 2; ++row) {
     // cells (x - 1, row) and (x, row) along t: row 0 at t - 1, row 1 at t
@@ -513,11 +518,21 @@ __host__ __device__ __forceinline__ S edge_px_point(const PatchDev& P, int g, in
     #pragma unroll
     for (int h = 0; h < 2; ++h)
       corner_from(v[h], sla[h], slb[h], BA[h], tA[h], BB[h], tB[h], sa[h], sb[h], c, C[h]);
-    u.add(kk[0], C[0], c);
-    u.add(kk[1], C[1], c);
+    if constexpr (EMF == 1) {
+      #pragma unroll
+      for (int h = 0; h < 2; ++h)
+        #pragma unroll
+        for (int t = 0; t < 7; ++t) Call[kk[h]][t] = C[h][t];
+    } else {
+      u.add(kk[0], C[0], c);
+      u.add(kk[1], C[1], c);
+    }
     MHD_SCHED_FENCE();
   }
-  return u.finish(c);
+  if constexpr (EMF == 1)
+    return uct_hlld_emf(Call, c);
+  else
+    return u.finish(c);
 }
 
 // ------------------------------------------------ forward writers of stages 1-3
@@ -573,10 +588,10 @@ __host__ __device__ __forceinline__ void face_flux_item(const PatchDev& P, int g
   face_point(P, g, d, i, j, k, LdRel<T>{Win + P.wbase}, c, F);
 }
 
-template <typename T>
+template <int EMF, typename T>
 __host__ __device__ __forceinline__ T edge_emf_item(const PatchDev& P, int g, int e, int i, int j, int k,
                                                     const T* Win, const Consts<T>& c) {
-  return edge_point(P, g, e, i, j, k, LdRel<T>{Win + P.wbase}, c);
+  return edge_point<EMF>(P, g, e, i, j, k, LdRel<T>{Win + P.wbase}, c);
 }
 
 // -------------------------------------------------------------- time step
@@ -801,7 +816,8 @@ __host__ __device__ __forceinline__ T adj_w_item(const PatchDev& P, int g, const
         y[a] += sa;
         y[b] += sb;
         if (!edge_computed(P, g, e, y)) continue;
-        const S em = edge_point(P, g, e, y[0], y[1], y[2], acc, cd);
+        const S em = c.emf == 1 ? edge_point<1>(P, g, e, y[0], y[1], y[2], acc, cd)
+                                : edge_point<0>(P, g, e, y[0], y[1], y[2], acc, cd);
         sum = sum + lam_emf(P, g, lam, e, y, dtdx) * em.d;
       }
   }
@@ -1056,7 +1072,7 @@ __host__ __device__ __forceinline__ void copy_tile(X& ex, const PatchDev& P, int
 // edge by a FORM 3 pass into the scratch slots of the time-n EMFs (P.sbase + (8 + e) Nc);
 // FORM 3: that pass -- the edges the tile owns (its cells' lower edges, plus the upper layer
 // where the tile ends the patch), written to the scratch, no update.
-template <typename T, int TX, int TY, int TZ, int FORM, class X>
+template <typename T, int TX, int TY, int TZ, int FORM, int EMF, class X>
 __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDev& P, int g,
                                                     const TileDev& tl, const T* Uin, T* Uout,
                                                     const T* Win, double dt, const double* dxp,
@@ -1127,11 +1143,11 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         const int64_t cg = cell_of(P, i0 + lx, j0 + ly, k0 + lz);
         T* eo = const_cast<T*>(eg) + e * Nc + cg;
         if (PR && e == 1)
-          eo[0] = edge_px_point<1>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
+          eo[0] = edge_px_point<1, EMF>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
         else if (PR && e == 2)
-          eo[0] = edge_px_point<2>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
+          eo[0] = edge_px_point<2, EMF>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
         else
-          eo[0] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
+          eo[0] = edge_emf_item<EMF>(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
       }
       return;
     }
@@ -1182,11 +1198,11 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         T* ed = e == 0 ? exx : (e == 1 ? ey : ez);
         const int li = lx + LX * (ly + LY * lz);
         if (PR && e == 1)
-          ed[li] = edge_px_point<1>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
+          ed[li] = edge_px_point<1, EMF>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
         else if (PR && e == 2)
-          ed[li] = edge_px_point<2>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
+          ed[li] = edge_px_point<2, EMF>(P, g, i0 + lx, j0 + ly, k0 + lz, wa, c);
         else
-          ed[li] = edge_emf_item(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
+          ed[li] = edge_emf_item<EMF>(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
       }
     }
     ex.sync();

@@ -28,12 +28,12 @@ def test_library_exports_every_declared_symbol(B):
 def _desc(B, dims, **kw):
     dims = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
     base = dict(guard=3, precision=8, gamma=5 / 3, cfl=0.4, limiter=0, rho_floor=1e-12,
-                p_floor=1e-12, eps_deg=1e-10, max_scratch_bytes=0)
+                p_floor=1e-12, eps_deg=1e-10, max_scratch_bytes=0, emf_solver=0)
     base.update(kw)
     d = B.mhd_bunch_desc(dims.shape[0], dims.ctypes.data_as(C.POINTER(C.c_int32)), base["guard"],
                          base["precision"], base["gamma"], base["cfl"], base["limiter"],
                          base["rho_floor"], base["p_floor"], base["eps_deg"],
-                         base["max_scratch_bytes"])
+                         base["max_scratch_bytes"], base["emf_solver"])
     return d, dims
 
 
@@ -52,6 +52,7 @@ def _create(B, dims, **kw):
     (dict(), [[2, 16, 16]]),                  # an active direction narrower than g
     (dict(), [[16, 0, 16]]),
     (dict(rho_floor=0.0), [[16, 16, 16]]),
+    (dict(emf_solver=2), [[16, 16, 16]]),     # edge EMF: 0 UCT-HLL, 1 UCT-HLLD
     (dict(), np.zeros((0, 3))),               # no patches
 ])
 def test_create_rejects_invalid_descriptions(B, kw, dims):

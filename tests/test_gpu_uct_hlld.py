@@ -1,0 +1,188 @@
+"""GPU parity of the UCT-HLLD edge EMF (emf_solver = 1; reading R21, §2.1 "Constrained
+transport and 2D-extension of the HLLD solver", Fig. 3) against the oracle with the same
+solver, through the C ABI.
+
+* One update, FP64, per-step bar 1e-12 (per-field metric of gpu_util.rel_err_fields) on
+  the step-parity cases of every dimensionality and layout.
+* Every launch configuration (tile shape x launch mode x solver form x predictor mode) gives
+  the same bits, in FP64 and FP32; the common result is within the per-step bar.
+* Orszag-Tang 64^2: 100 FP64 steps, each from the oracle's state and time step (1e-12 per
+  step); the FP32 run with the oracle's time steps fed in against the FP64 oracle (L1 1e-5).
+* The adjoint of one update with this EMF: <J v, w> from the oracle's dual numbers equals
+  <v, J^T w> from the GPU adjoint.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, l1_rel_fields, log, make_bunch, rel_err_fields
+from paper_2508_09568_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_STEP_TOL = 1e-12
+
+
+def _prm(oracle, gam):
+    return oracle.Params(gamma=gam, emf_solver=1)
+
+
+def _case(name):
+    import mhdtest as mt
+    import oracle
+    if name == "ot64":
+        w = W.orszag_tang(64, 32)
+        L, U, dx, nbr, gam = w.layout, w.U, w.dx, w.nbr, w.gamma
+    elif name == "wave2d_yz":
+        L0, U0, dx0, _, _ = mt.linear_wave_2d(32, "fast", amp=0.1)
+        U, L, dx, grid = mt.cyclic_permute(U0, L0, dx0, (2, 2, 1), 1)
+        nbr = W.grid_neighbours(grid, (True, True, True))
+        gam = 5 / 3
+    elif name == "wave2d_zx":
+        L0, U0, dx0, _, _ = mt.linear_wave_2d(32, "alfven", amp=0.1)
+        U, L, dx, grid = mt.cyclic_permute(U0, L0, dx0, (2, 2, 1), 2)
+        nbr = W.grid_neighbours(grid, (True, True, True))
+        gam = 5 / 3
+    elif name == "sod8":
+        w = W.sod(128, patches=8)
+        L, U, dx, nbr, gam = w.layout, w.U, w.dx, w.nbr, w.gamma
+    elif name == "turb3d":
+        w = W.turbulence(N=32, patch=16)
+        L, U, dx, nbr, gam = w.layout, w.U.numpy(), w.dx, w.nbr, w.gamma
+    elif name == "ragged3d":
+        w = W.uneven(mix=((9, 3), (13, 2), (20, 2)))
+        L, U, dx, nbr, gam = w.layout, w.U.numpy(), w.dx, None, w.gamma
+    elif name == "adjoint32":
+        w = W.adjoint_case(N=32, patch=16)
+        L, U, dx, nbr, gam = w.layout, w.U, w.dx, w.nbr, w.gamma
+    else:
+        raise KeyError(name)
+    U = np.ascontiguousarray(U, dtype=np.float64).copy()
+    if nbr is not None:
+        oracle.fill_guards(U, L.dims, L.g, nbr)
+    return L, U, np.ascontiguousarray(dx, dtype=np.float64), nbr, gam
+
+
+@pytest.mark.parametrize("name", ["ot64", "wave2d_yz", "wave2d_zx", "sod8", "turb3d",
+                                  "ragged3d", "adjoint32"])
+def test_step_parity_fp64(name):
+    import oracle
+    log(f"[gpu] uct-hlld step parity fp64 case={name}")
+    L, U, dx, nbr, gam = _case(name)
+    prm = _prm(oracle, gam)
+    dt = oracle.cfl_many(U, L.dims, L.g, dx, prm)
+    dt = np.full(L.P, dt.min()) if nbr is not None else dt
+    ref = oracle.step_many(U, L.dims, L.g, dt, dx, prm)
+    base = oracle.step_many(U, L.dims, L.g, dt, dx, oracle.Params(gamma=gam))
+    B = make_bunch(L, gam, emf_solver=1)
+    Uo = dev(np.zeros_like(U))
+    B.update(dev(U), Uo, dev(dt), dev(dx))
+    assert B.check() == 0
+    got = host(Uo)
+    err = rel_err_fields(L, got, ref)
+    log(f"    per-field rel err {err}; vs the UCT-HLL oracle {rel_err_fields(L, got, base).max():.2e}")
+    assert np.all(err <= FP64_STEP_TOL), err
+
+
+@pytest.mark.parametrize("case,precision", [("ragged3d", 8), ("ot64", 8), ("ragged3d", 4),
+                                            ("ot64", 4)])
+def test_every_launch_configuration_gives_identical_bits(case, precision):
+    import oracle
+    import torch
+    log(f"[gpu] uct-hlld launch configurations case={case} precision={precision}")
+    L, U, dx, nbr, gam = _case(case)
+    if precision == 4:
+        U = U.astype(np.float32).astype(np.float64)
+    prm = _prm(oracle, gam)
+    dt = oracle.cfl_many(U, L.dims, L.g, dx, prm)
+    dt = np.full(L.P, dt.min()) if nbr is not None else dt
+    ref = oracle.step_many(U, L.dims, L.g, dt, dx, prm)
+    B = make_bunch(L, gam, precision=precision, emf_solver=1)
+    dty = torch.float64 if precision == 8 else torch.float32
+    Ui, dtd, dxd = dev(U).to(dty), dev(dt), dev(dx)
+    first = None
+    n = 0
+    for fused in range(len(B.predictor_modes())):
+        B.set_predictor(fused)
+        for split in (0, 1, 2):
+            B.set_solver_split(split)
+            for i in range(len(B.tile_configs())):
+                B.set_tile(i)
+                Uo = torch.zeros_like(Ui)
+                B.update(Ui, Uo, dtd, dxd)
+                assert B.check() == 0
+                got = host(Uo)
+                n += 1
+                if first is None:
+                    first = got
+                    continue
+                for p in range(L.P):
+                    assert np.array_equal(L.interior(got, p), L.interior(first, p)), \
+                        (fused, split, i, p)
+    err = rel_err_fields(L, first, ref)
+    log(f"    {n} configurations identical; vs oracle per-field {err}")
+    assert np.all(err <= (FP64_STEP_TOL if precision == 8 else 2e-5)), err
+
+
+def test_orszag_tang_fp64_per_step_and_fp32_run():
+    import oracle
+    import torch
+    log("[gpu] uct-hlld Orszag-Tang 64^2: 100 FP64 steps per step, FP32 run")
+    w = W.orszag_tang(64, 32)
+    L = w.layout
+    prm = _prm(oracle, w.gamma)
+    U = np.ascontiguousarray(w.U, dtype=np.float64).copy()
+    B = make_bunch(L, w.gamma, emf_solver=1)
+    B32 = make_bunch(L, w.gamma, precision=4, emf_solver=1)
+    nbr = dev(w.nbr.astype(np.int32))
+    dxd = dev(w.dx)
+    U32 = dev(U).to(torch.float32)
+    worst = 0.0
+    for step in range(100):
+        oracle.fill_guards(U, L.dims, L.g, w.nbr)
+        dt = np.full(L.P, oracle.cfl_many(U, L.dims, L.g, w.dx, prm).min())
+        ref = oracle.step_many(U, L.dims, L.g, dt, w.dx, prm)
+        Uo = dev(np.zeros_like(U))
+        B.update(dev(U), Uo, dev(dt), dxd)
+        worst = max(worst, rel_err_fields(L, host(Uo), ref).max())
+        # FP32: its own state, the oracle's time step
+        B32.fill_guards(U32, nbr)
+        o32 = torch.zeros_like(U32)
+        B32.update(U32, o32, dev(dt), dxd)
+        U32 = o32
+        U = ref
+    assert B.check() == 0 and B32.check() == 0
+    B32.fill_guards(U32, nbr)
+    l1 = l1_rel_fields(L, host(U32), U)
+    log(f"    FP64 worst per-step {worst:.2e}; FP32 after 100 steps L1 per field {l1}")
+    assert worst <= FP64_STEP_TOL
+    assert np.all(l1 <= 1e-5), l1
+
+
+@pytest.mark.parametrize("name", ["ot64", "turb3d"])
+def test_adjoint_dot_product_against_oracle_jvp(name):
+    import oracle
+    log(f"[gpu] uct-hlld adjoint dot-product case={name}")
+    L, U, dx, nbr, gam = _case(name)
+    rng = np.random.default_rng(5)
+    U = U.copy()
+    M = np.zeros(L.total, dtype=bool)
+    for p in range(L.P):
+        L.interior(M, p)[...] = True
+    U[M] += 1e-3 * rng.standard_normal(int(M.sum()))   # no limiter case decided by a tie
+    oracle.fill_guards(U, L.dims, L.g, nbr)
+    prm = _prm(oracle, gam)
+    dt = np.full(L.P, 0.8 * oracle.cfl_many(U, L.dims, L.g, dx, prm).min())
+    v = rng.standard_normal(L.total) * M
+    oracle.fill_guards(v, L.dims, L.g, nbr)
+    wv = rng.standard_normal(L.total) * M
+    _, Jv = oracle.jvp_many(U, v, L.dims, L.g, dt, dx, prm)
+    B = make_bunch(L, gam, emf_solver=1)
+    B.adjoint_bind(nbr)
+    lam_in = dev(np.zeros(L.total))
+    B.adjoint(dev(U), dev(wv), lam_in, dev(dt), dev(dx))
+    assert B.check() == 0
+    JTw = host(lam_in)
+    a = float(np.dot(Jv[M], wv[M]))
+    b = float(np.dot(v[M], JTw[M]))
+    log(f"    <Jv,w>={a:.16e} <v,J^T w>={b:.16e} rel={abs(a - b) / abs(a):.2e}")
+    assert abs(a - b) <= 1e-12 * abs(a)
