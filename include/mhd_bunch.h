@@ -264,6 +264,41 @@ mhd_status mhd_bunch_graph_capture(mhd_bunch* h, int32_t nsteps, void* U_a, void
                                    int32_t dt_mode, hipStream_t stream);
 mhd_status mhd_bunch_graph_launch(mhd_bunch* h, hipStream_t stream);
 
+/* ---- bunches whose state stays in host memory (§2.4 "DISPATCH Integration": patches are
+ * bunched on the host and sent to the GPU, three bunches active at once -- one being
+ * filled, one computed, one emptied; §3.2: a third of the time went to transfers; §4:
+ * asynchronous transfers hide them) ----
+ * mhd_stream_create cuts a bunch description into consecutive sub-bunches of at most
+ * `patches_per_bunch` patches (one internal bunch handle each) and plans `slots` (1..8)
+ * device slots, each holding one sub-bunch's input and output state.  The caller provides
+ * one device allocation of mhd_stream_device_bytes (tables of every sub-bunch, one shared
+ * predictor scratch, dt/dx, the slots; 256-byte aligned) to mhd_stream_bind, which uploads
+ * the tables on `stream` and creates three non-blocking streams of default priority.
+ * mhd_stream_update advances a host-resident state U_in (guards filled, layout of the whole
+ * description) into the host buffer U_out with host arrays dt[P], dx[P][3]: per sub-bunch,
+ * copy in (first stream), update (second stream; the output slot starts as a copy of the
+ * input, so U_out's guard entries are U_in's), copy out (third stream), ordered by events,
+ * so that with slots >= 2 the copies of neighbouring sub-bunches overlap the update.  All
+ * work is ordered after earlier work on `stream`, and later work on `stream` waits for every
+ * copy out; the call itself returns without synchronising.  The host buffers must stay valid
+ * and unchanged until then and should be page-locked (hipHostMalloc) for the copies to run
+ * asynchronously.  U_in and U_out must not overlap.  mhd_stream_configure applies one launch
+ * configuration (mhd_bunch_tile_set index, predictor mode, solver form) to every sub-bunch;
+ * mhd_stream_check synchronises `stream` and reports the sub-bunches' device status as
+ * mhd_bunch_check does.  Results are those of mhd_bunch_update on the same state. */
+typedef struct mhd_stream mhd_stream;
+mhd_status mhd_stream_create(mhd_stream** out, const mhd_bunch_desc* desc, int32_t patches_per_bunch,
+                             int32_t slots);
+void mhd_stream_destroy(mhd_stream* s);
+int64_t mhd_stream_device_bytes(const mhd_stream* s);
+int32_t mhd_stream_bunch_count(const mhd_stream* s);
+mhd_status mhd_stream_bind(mhd_stream* s, void* device_buffer, hipStream_t stream);
+mhd_status mhd_stream_configure(mhd_stream* s, int32_t tile, int32_t predictor, int32_t split);
+mhd_status mhd_stream_update(mhd_stream* s, const void* U_in_host, void* U_out_host,
+                             const double* dt_host, const double* dx_host, hipStream_t stream);
+mhd_status mhd_stream_check(mhd_stream* s, hipStream_t stream);
+const char* mhd_stream_last_error(const mhd_stream* s);
+
 /* Synchronises `stream`, then returns MHD_ENONPHYS if any kernel since the last check
  * met a non-physical state, MHD_EINVAL if a guard fill met an inconsistent neighbour table or
  * a local time step met a step that is not finite and > 0 (and clears the flags), else

@@ -103,6 +103,15 @@ _SIGS = {
     "mhd_bunch_predictor_shape": (C.c_int, [_h, C.c_int32, _v]),
     "mhd_bunch_set_solver_split": (C.c_int, [_h, C.c_int32]),
     "mhd_bunch_solver_split": (C.c_int32, [_h]),
+    "mhd_stream_create": (C.c_int, [C.POINTER(_h), C.POINTER(mhd_bunch_desc), C.c_int32, C.c_int32]),
+    "mhd_stream_destroy": (None, [_h]),
+    "mhd_stream_device_bytes": (C.c_int64, [_h]),
+    "mhd_stream_bunch_count": (C.c_int32, [_h]),
+    "mhd_stream_bind": (C.c_int, [_h, _v, _st]),
+    "mhd_stream_configure": (C.c_int, [_h, C.c_int32, C.c_int32, C.c_int32]),
+    "mhd_stream_update": (C.c_int, [_h, _v, _v, _v, _v, _st]),
+    "mhd_stream_check": (C.c_int, [_h, _st]),
+    "mhd_stream_last_error": (C.c_char_p, [_h]),
 }
 
 STATIC_SCRATCH_BYTES = 128 << 20   # MHD_STATIC_SCRATCH_BYTES of include/mhd_bunch.h
@@ -389,3 +398,67 @@ class Bunch:
     def graph_launch(self, stream=None):
         _ok(mhd_bunch_graph_launch(self._h, _stream(stream)), "mhd_bunch_graph_launch", self._h)
 
+
+class Stream:
+    """A bunch whose state stays in host memory, streamed through the device in sub-bunches
+    of at most `patches_per_bunch` patches over `slots` device slots (copy in, update, copy
+    out on three streams).  State buffers are flat host tensors (pinned for overlap)."""
+
+    def __init__(self, dims, patches_per_bunch, slots=3, g=3, precision=8, gamma=5.0 / 3.0,
+                 cfl=0.4, limiter=0, rho_floor=1e-12, p_floor=1e-12, eps_deg=1e-10,
+                 emf_solver=0, device="cuda", stream=None):
+        import numpy as np
+        import torch
+        self._dims = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
+        d = mhd_bunch_desc(self._dims.shape[0], self._dims.ctypes.data_as(_ip), g, precision,
+                           gamma, cfl, limiter, rho_floor, p_floor, eps_deg, 0, emf_solver)
+        h = _h()
+        _ok(mhd_stream_create(C.byref(h), C.byref(d), int(patches_per_bunch), int(slots)),
+            "mhd_stream_create")
+        self._h = h
+        self.P = int(self._dims.shape[0])
+        self.precision = precision
+        self.dtype = torch.float64 if precision == 8 else torch.float32
+        dv = torch.device(device)
+        if dv.type == "cuda" and dv.index is None:
+            dv = torch.device("cuda", torch.cuda.current_device())
+        self.device = dv
+        ncell = np.prod(np.where(self._dims > 1, self._dims + 2 * g, 1), axis=1)
+        self.state_elems = int(8 * ncell.sum())
+        self.buffer = torch.empty(int(mhd_stream_device_bytes(h)), dtype=torch.uint8, device=dv)
+        code = mhd_stream_bind(h, _ptr(self.buffer), _stream(stream))
+        if code != MHD_OK:
+            raise MhdError(code, "mhd_stream_bind", mhd_stream_last_error(h).decode())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            mhd_stream_destroy(h)
+            self._h = None
+
+    def bunches(self):
+        return int(mhd_stream_bunch_count(self._h))
+
+    def configure(self, tile, predictor, split):
+        _ok(mhd_stream_configure(self._h, int(tile), int(predictor), int(split)),
+            "mhd_stream_configure")
+
+    def _check_host(self, t, dtype, n, what):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.device.type != "cpu" or t.dtype != dtype \
+                or t.numel() != n or not t.is_contiguous():
+            raise ValueError(f"{what}: a contiguous host {dtype} tensor of {n} elements is required")
+
+    def update(self, U_in, U_out, dt, dx, stream=None):
+        import torch
+        self._check_host(U_in, self.dtype, self.state_elems, "U_in")
+        self._check_host(U_out, self.dtype, self.state_elems, "U_out")
+        self._check_host(dt, torch.float64, self.P, "dt")
+        self._check_host(dx, torch.float64, 3 * self.P, "dx")
+        code = mhd_stream_update(self._h, _ptr(U_in), _ptr(U_out), _ptr(dt), _ptr(dx),
+                                 _stream(stream))
+        if code != MHD_OK:
+            raise MhdError(code, "mhd_stream_update", mhd_stream_last_error(self._h).decode())
+
+    def check(self, stream=None):
+        return mhd_stream_check(self._h, _stream(stream))

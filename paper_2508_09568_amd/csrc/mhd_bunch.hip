@@ -686,7 +686,9 @@ struct mhd_bunch {
   unsigned long long* d_smax() const { return (unsigned long long*)(ws + o_smax); }
   int* d_status() const { return (int*)(ws + o_status); }
   int32_t* d_ready() const { return (int32_t*)(ws + o_ready); }
-  void* d_scratch() const { return ws + o_scratch; }
+  // the scratch of a sub-bunch of a host-streamed bunch lives in the stream's shared region
+  char* scratch_ext = nullptr;
+  void* d_scratch() const { return scratch_ext ? (void*)scratch_ext : (void*)(ws + o_scratch); }
 };
 
 namespace {
@@ -1002,6 +1004,38 @@ mhd_status launch_lts_step(mhd_bunch* h, T* Ucur, T* Unew, T* Uprev, double* t, 
 }
 
 }  // namespace
+
+// ------------------------------------------------------------ host-streamed bunches
+// A bunch whose state stays in host memory is cut into consecutive sub-bunches; each update
+// streams them through `slots` device slots on three streams (copy in, compute, copy out),
+// so that the copy of sub-bunch j+1 in, the update of j and the copy of j-1 out overlap.
+struct mhd_stream {
+  std::vector<mhd_bunch*> sub;       // one handle per sub-bunch (tables in `dev`)
+  std::vector<int> p0;               // first patch of each sub-bunch (p0[nsub] = P)
+  std::vector<int64_t> base;         // element offset of each sub-bunch in the state
+  int P = 0, prec = 8, slots = 3;
+  int64_t slot_elems = 0;            // largest sub-bunch state
+  size_t o_scratch = 0, o_dt = 0, o_dx = 0, o_slot = 0, bytes = 0;
+  std::vector<size_t> o_tab;         // table region of each sub-bunch
+  char* dev = nullptr;
+  bool bound = false;
+  hipStream_t st[3] = {nullptr, nullptr, nullptr};   // copy in, compute, copy out
+  std::vector<hipEvent_t> ev;        // per slot: input ready, compute done, output done; + start
+  char last_error[256] = {0};
+  ~mhd_stream() {
+    for (mhd_bunch* b : sub) delete b;
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipStream_t x : st)
+      if (x) (void)hipStreamDestroy(x);
+  }
+  char* slot_in(int k) const { return dev + o_slot + (size_t)(2 * k) * align256((size_t)slot_elems * prec); }
+  char* slot_out(int k) const { return slot_in(k) + align256((size_t)slot_elems * prec); }
+  bool ok(hipError_t e, const char* what) {
+    if (e == hipSuccess) return true;
+    snprintf(last_error, sizeof(last_error), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    return false;
+  }
+};
 
 // ------------------------------------------------------------------------ C ABI
 
@@ -1601,6 +1635,162 @@ mhd_status mhd_bunch_graph_capture(mhd_bunch* h, int32_t nsteps, void* U_a, void
   if (st != MHD_OK) h->drop_graph();
   return st;
 }
+
+mhd_status mhd_stream_create(mhd_stream** out, const mhd_bunch_desc* d, int32_t per_bunch,
+                             int32_t slots) {
+  if (!out || !d || !d->dims || d->n_patches < 1 || per_bunch < 1 || slots < 1 || slots > 8)
+    return MHD_EINVAL;
+  mhd_stream* S = new (std::nothrow) mhd_stream;
+  if (!S) return MHD_ENOMEM;
+  S->P = d->n_patches;
+  S->prec = d->precision;
+  S->slots = slots;
+  size_t o = 0, scratch = 0;
+  int64_t base = 0;
+  for (int p = 0; p < d->n_patches; p += per_bunch) {
+    mhd_bunch_desc sd = *d;
+    sd.n_patches = std::min(per_bunch, d->n_patches - p);
+    sd.dims = d->dims + 3 * p;
+    mhd_bunch* h = nullptr;
+    const mhd_status st = mhd_bunch_create(&h, &sd);
+    if (st != MHD_OK) {
+      delete S;
+      return st;
+    }
+    S->sub.push_back(h);
+    S->p0.push_back(p);
+    S->base.push_back(base);
+    base += h->state_elems;
+    S->slot_elems = std::max(S->slot_elems, h->state_elems);
+    scratch = std::max(scratch, (size_t)h->scratch_elems * h->prec);
+    S->o_tab.push_back(o);
+    o = align256(o + h->o_scratch);       // the tables only: the scratch is shared
+  }
+  S->p0.push_back(d->n_patches);
+  S->base.push_back(base);
+  S->o_scratch = o;
+  o = align256(o + scratch);
+  S->o_dt = o;
+  o = align256(o + sizeof(double) * S->P);
+  S->o_dx = o;
+  o = align256(o + 3 * sizeof(double) * S->P);
+  S->o_slot = o;
+  o += (size_t)(2 * slots) * align256((size_t)S->slot_elems * S->prec);
+  S->bytes = o;
+  *out = S;
+  return MHD_OK;
+}
+
+void mhd_stream_destroy(mhd_stream* S) { delete S; }
+
+int64_t mhd_stream_device_bytes(const mhd_stream* S) { return S ? (int64_t)S->bytes : -1; }
+
+int32_t mhd_stream_bunch_count(const mhd_stream* S) { return S ? (int32_t)S->sub.size() : -1; }
+
+mhd_status mhd_stream_bind(mhd_stream* S, void* dev, hipStream_t s) {
+  if (!S || !dev || ((uintptr_t)dev & 255)) return MHD_EINVAL;
+  S->dev = (char*)dev;
+  S->last_error[0] = 0;
+  for (size_t j = 0; j < S->sub.size(); ++j) {
+    mhd_bunch* h = S->sub[j];
+    const mhd_status st = mhd_bunch_bind(h, S->dev + S->o_tab[j], s);
+    if (st != MHD_OK) {
+      snprintf(S->last_error, sizeof(S->last_error), "sub-bunch %zu: %s", j, h->last_error);
+      return st;
+    }
+    h->scratch_ext = S->dev + S->o_scratch;
+  }
+  if (!S->st[0])
+    for (int k = 0; k < 3; ++k)
+      if (!S->ok(hipStreamCreateWithFlags(&S->st[k], hipStreamNonBlocking), "create stream"))
+        return MHD_EDEVICE;
+  if (S->ev.empty()) {
+    S->ev.resize(3 * S->slots + 1, nullptr);
+    for (hipEvent_t& e : S->ev)
+      if (!S->ok(hipEventCreateWithFlags(&e, hipEventDisableTiming), "create event"))
+        return MHD_EDEVICE;
+  }
+  S->bound = true;
+  return MHD_OK;
+}
+
+mhd_status mhd_stream_configure(mhd_stream* S, int32_t tile, int32_t predictor, int32_t split) {
+  if (!S) return MHD_EINVAL;
+  for (mhd_bunch* h : S->sub) {
+    mhd_status st = mhd_bunch_tile_set(h, tile);
+    if (st == MHD_OK) st = mhd_bunch_set_predictor(h, predictor);
+    if (st == MHD_OK) st = mhd_bunch_set_solver_split(h, split);
+    if (st != MHD_OK) return st;
+  }
+  return MHD_OK;
+}
+
+mhd_status mhd_stream_update(mhd_stream* S, const void* Uin, void* Uout, const double* dt,
+                             const double* dx, hipStream_t s) {
+  if (!S || !Uin || !Uout || !dt || !dx || Uin == Uout) return MHD_EINVAL;
+  if (!S->bound) return MHD_ESTATE;
+  const size_t es = S->prec;
+  const size_t total = (size_t)S->base.back() * es;
+  const char *a = (const char*)Uin, *b = (const char*)Uout;
+  if (a < b + total && b < a + total) return MHD_EINVAL;
+  const int K = S->slots, nsub = (int)S->sub.size();
+  hipEvent_t* ev_in = S->ev.data();
+  hipEvent_t* ev_comp = ev_in + K;
+  hipEvent_t* ev_out = ev_comp + K;
+  hipEvent_t ev_start = ev_out[K];
+  hipStream_t up = S->st[0], comp = S->st[1], down = S->st[2];
+  double* ddt = (double*)(S->dev + S->o_dt);
+  double* ddx = (double*)(S->dev + S->o_dx);
+  bool ok = S->ok(hipEventRecord(ev_start, s), "record start");
+  for (int k = 0; k < 3 && ok; ++k) ok = S->ok(hipStreamWaitEvent(S->st[k], ev_start, 0), "wait start");
+  ok = ok && S->ok(hipMemcpyAsync(ddt, dt, sizeof(double) * S->P, hipMemcpyHostToDevice, up), "copy dt") &&
+       S->ok(hipMemcpyAsync(ddx, dx, 3 * sizeof(double) * S->P, hipMemcpyHostToDevice, up), "copy dx");
+  for (int j = 0; j < nsub && ok; ++j) {
+    const int k = j % K;
+    mhd_bunch* h = S->sub[j];
+    const size_t off = (size_t)S->base[j] * es, nb = (size_t)h->state_elems * es;
+    char* in = S->slot_in(k);
+    char* outb = S->slot_out(k);
+    // copy in: the slot's input is free once the update of sub-bunch j - K has read it
+    if (j >= K) ok = S->ok(hipStreamWaitEvent(up, ev_comp[k], 0), "wait slot input");
+    ok = ok && S->ok(hipMemcpyAsync(in, (const char*)Uin + off, nb, hipMemcpyHostToDevice, up), "copy in") &&
+         S->ok(hipEventRecord(ev_in[k], up), "record input");
+    // compute: its output is free once sub-bunch j - K has been copied out
+    ok = ok && S->ok(hipStreamWaitEvent(comp, ev_in[k], 0), "wait input");
+    if (j >= K) ok = ok && S->ok(hipStreamWaitEvent(comp, ev_out[k], 0), "wait slot output");
+    // the output carries the input's guards (the update writes owned values only)
+    ok = ok && S->ok(hipMemcpyAsync(outb, in, nb, hipMemcpyDeviceToDevice, comp), "copy guards");
+    if (ok) {
+      const mhd_status st = mhd_bunch_update(h, in, outb, ddt + S->p0[j], ddx + 3 * S->p0[j], comp);
+      if (st != MHD_OK) {
+        snprintf(S->last_error, sizeof(S->last_error), "update of sub-bunch %d: %s", j, h->last_error);
+        return st;
+      }
+    }
+    ok = ok && S->ok(hipEventRecord(ev_comp[k], comp), "record compute");
+    // copy out
+    ok = ok && S->ok(hipStreamWaitEvent(down, ev_comp[k], 0), "wait compute") &&
+         S->ok(hipMemcpyAsync((char*)Uout + off, outb, nb, hipMemcpyDeviceToHost, down), "copy out") &&
+         S->ok(hipEventRecord(ev_out[k], down), "record output");
+  }
+  // the caller's stream continues after every copy out
+  for (int k = 0; k < std::min(K, nsub) && ok; ++k)
+    ok = S->ok(hipStreamWaitEvent(s, ev_out[k], 0), "join");
+  return ok ? MHD_OK : MHD_EDEVICE;
+}
+
+mhd_status mhd_stream_check(mhd_stream* S, hipStream_t s) {
+  if (!S) return MHD_EINVAL;
+  if (!S->bound) return MHD_ESTATE;
+  mhd_status worst = MHD_OK;
+  for (mhd_bunch* h : S->sub) {
+    const mhd_status st = mhd_bunch_check(h, s);
+    if (st != MHD_OK && worst == MHD_OK) worst = st;
+  }
+  return worst;
+}
+
+const char* mhd_stream_last_error(const mhd_stream* S) { return S ? S->last_error : "null handle"; }
 
 mhd_status mhd_bunch_graph_launch(mhd_bunch* h, hipStream_t s) {
   if (!h) return MHD_EINVAL;
