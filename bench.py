@@ -373,6 +373,100 @@ def run_lts(w, tile, t_mult):
     return res
 
 
+def run_stream(w, tile, per_bunch=256):
+    """The 512^3 turbulence (FP32) held in page-locked host memory and streamed through the
+    device for one update: sub-bunches of `per_bunch` patches, copy in / update / copy out on
+    three streams over 3 device slots (overlapped) and over 1 slot (serial).  Time on the
+    current stream from the first copy in to the last copy out (the PCIe-inclusive rate)."""
+    import numpy as np
+    import torch
+
+    from paper_2508_09568_amd.binding import Bunch, Stream
+
+    L = w.layout
+    nbr = torch.as_tensor(w.nbr.astype(np.int32)).cuda()
+    dx = torch.as_tensor(w.dx).cuda()
+    B = Bunch(L.dims, g=L.g, precision=4, gamma=w.gamma, cfl=w.cfl)
+    Ud = w.U.to(dtype=torch.float32, copy=True)
+    dt = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    B.fill_guards(Ud, nbr)
+    B.cfl(Ud, dx, dt, global_min=True)
+    cfg = B.tile_configs().index(tuple(tile["chosen"]))
+    B.set_tile(cfg)
+    B.set_predictor(tile["fused_predictor"])
+    B.set_solver_split(tile["solver_split"])
+    Ur = torch.empty_like(Ud)
+    B.update(Ud, Ur, dt, dx)
+    Uh = torch.empty(Ud.numel(), dtype=torch.float32, pin_memory=True)
+    Uh.copy_(Ud)
+    Uo = torch.empty_like(Uh).pin_memory()
+    dth, dxh = dt.cpu(), dx.reshape(-1).cpu()
+    del Ud
+    torch.cuda.empty_cache()
+    nbytes = 2 * Uh.numel() * 4
+    cells = int(L.interior_cells)
+    out = {"workload": f"512^3 turbulence, FP32, in page-locked host memory; sub-bunches of "
+                       f"{per_bunch} patches", "bytes_per_update": nbytes}
+    for slots in (3, 1):
+        S = Stream(L.dims, per_bunch, slots=slots, precision=4, gamma=w.gamma, cfl=w.cfl)
+        S.configure(cfg, tile["fused_predictor"], tile["solver_split"])
+        S.update(Uh, Uo, dth, dxh)            # warm-up
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        S.update(Uh, Uo, dth, dxh)
+        b.record()
+        torch.cuda.synchronize()
+        if S.check() != 0:
+            raise RuntimeError("device status after the streamed update")
+        ms = a.elapsed_time(b)
+        out[f"slots_{slots}"] = {"ms": ms, "cell_updates_per_s": cells / (ms * 1e-3),
+                                 "pcie_gbs": nbytes / (ms * 1e-3) / 1e9,
+                                 "sub_bunches": S.bunches()}
+        del S
+        torch.cuda.empty_cache()
+    # sampled patches against the resident update
+    ref = Ur.cpu()
+    bad = 0.0
+    for p in (0, L.P // 2, L.P - 1):
+        a0, a1 = int(L.base[p]), int(L.base[p + 1])
+        own = _owned_in_block(L, p)
+        bad = max(bad, float(np.abs(Uo.numpy()[a0:a1][own] - ref.numpy()[a0:a1][own]).max()))
+    out["max_abs_diff_vs_resident"] = bad
+    # no pipeline: the whole state copied in, updated, copied out, one after the other
+    Ud = torch.empty(Uh.numel(), dtype=torch.float32, device="cuda")
+    Uo2 = torch.empty_like(Ud)
+    dtd = dth.cuda()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    Ud.copy_(Uh, non_blocking=True)
+    B.update(Ud, Uo2, dtd, dx)
+    Uo.copy_(Uo2, non_blocking=True)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    out["whole_state_serial"] = {"ms": ms, "cell_updates_per_s": cells / (ms * 1e-3),
+                                 "launch": "copy the whole state in, update, copy it out"}
+    del Ud, Uo2
+    torch.cuda.empty_cache()
+    out["pipeline_speedup_vs_serial"] = out["whole_state_serial"]["ms"] / out["slots_3"]["ms"]
+    out["overlap_speedup"] = out["slots_1"]["ms"] / out["slots_3"]["ms"]
+    return out
+
+
+def _owned_in_block(L, p):
+    """Boolean mask of patch p's owned entries inside its own block of the state."""
+    import numpy as np
+    from paper_2508_09568_amd import workloads as W
+    Lp = W.Layout(L.dims[p][None], L.g)
+    m = np.zeros(Lp.total, dtype=bool)
+    Lp.interior(m, 0)[...] = True
+    return m
+
+
 def cpu_baseline(block):
     """The oracle's step on a corner block of block^3 patches of the same seeded turbulence
     (same cell size and patch shape), generated on the host; guards filled by the oracle
@@ -394,11 +488,117 @@ def cpu_baseline(block):
     el = time.perf_counter() - t0
     cells = int(np.prod(L.dims.astype(np.int64), axis=1).sum())
     nth = oracle.threads()
+    # one thread: the first 64 patches of the same block
+    n1 = min(64, L.P)
+    end = int(L.base[n1])
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.step_many(np.ascontiguousarray(U[:end]), L.dims[:n1], L.g, np.full(n1, dt),
+                         w.dx[:n1], prm)
+        el1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(nth)
+    cells1 = int(np.prod(L.dims[:n1].astype(np.int64), axis=1).sum())
     return {"value": cells / el, "unit": "cell-updates/s", "cores": nth, "kind": "oracle",
             "sample": f"{L.P} patches of 32^3 ({block}^3 corner block of the 512^3 turbulence, "
                       f"FP64), one update: {cells} cell-updates in {el:.2f} s on {nth} threads "
                       f"(~{el * nth:.0f} thread-seconds)",
+            "single_thread": {"value": cells1 / el1, "unit": "cell-updates/s", "cores": 1,
+                              "sample": f"the first {n1} patches of that block, one update: "
+                                        f"{cells1} cell-updates in {el1:.2f} s on 1 thread"},
             "cpu": _cpu_model()}
+
+
+def cpu_baseline_uneven():
+    """The oracle's step of the whole uneven bunch (3600 patches of four sizes, each at its own
+    CFL step, frozen guards), in FP64 on all host threads.  The state is generated on the GPU
+    by the same generator as the GPU run and copied to the host."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2508_09568_amd import workloads as W
+
+    w = W.uneven(device="cuda", dtype=torch.float64)
+    L, dx, prm = w.layout, w.dx, oracle.Params(gamma=w.gamma, cfl=w.cfl)
+    U = w.U.cpu().numpy()
+    del w
+    torch.cuda.empty_cache()
+    dt = oracle.cfl_many(U, L.dims, L.g, dx, prm)
+    t0 = time.perf_counter()
+    oracle.step_many(U, L.dims, L.g, dt, dx, prm)
+    el = time.perf_counter() - t0
+    cells = int(L.interior_cells)
+    nth = oracle.threads()
+    return {"value": cells / el, "unit": "cell-updates/s", "cores": nth, "kind": "oracle",
+            "sample": f"one step of all {L.P} patches ({cells} cell-updates, FP64, own CFL "
+                      f"steps) in {el:.2f} s on {nth} threads"}
+
+
+def run_adjoint(reps):
+    """Adjoint workload (64^3 periodic as 8 patches of 32^3, FP64, fast wave + noise): 20 steps
+    at the fixed time step of the noise-free state, checkpoint every 5; gradient of the L2
+    misfit of the final density against the seeded target.  Times the forward rollout alone
+    and forward + backward (HIP events on the current stream, mean of `reps`)."""
+    import numpy as np
+    import torch
+
+    from paper_2508_09568_amd import workloads as W
+    from paper_2508_09568_amd.autodiff import rollout
+    from paper_2508_09568_amd.binding import Bunch
+
+    nsteps, every = 20, 5
+    w = W.adjoint_case()
+    L = w.layout
+    B = Bunch(L.dims, g=L.g, precision=8, gamma=w.gamma, cfl=w.cfl)
+    B.adjoint_bind(w.nbr)
+    nbr = torch.as_tensor(w.nbr.astype(np.int32)).cuda()
+    dx = torch.as_tensor(w.dx).cuda()
+    Uc = torch.as_tensor(W.adjoint_case(noise=0.0).U).cuda()
+    dt = torch.zeros(L.P, dtype=torch.float64, device="cuda")
+    B.fill_guards(Uc, nbr)
+    B.cfl(Uc, dx, dt, global_min=True)
+    dts = dt.expand(nsteps, L.P).contiguous()
+    mask = np.zeros(L.total)
+    for p in range(L.P):
+        L.interior(mask, p)[0] = 1.0
+    mask = torch.as_tensor(mask).cuda()
+    with torch.no_grad():
+        rho_t = rollout(torch.as_tensor(W.adjoint_case(noise_seed=6).U).cuda(), B, nbr, dts, dx,
+                        every) * mask
+    U0 = torch.as_tensor(w.U).cuda()
+
+    def fwd():
+        with torch.no_grad():
+            return rollout(U0, B, nbr, dts, dx, every)
+
+    def fwd_bwd():
+        x = U0.clone().requires_grad_(True)
+        r = rollout(x, B, nbr, dts, dx, every) * mask
+        (0.5 * ((r - rho_t) ** 2).sum()).backward()
+        return x.grad
+
+    out = {}
+    for key, fn in (("forward", fwd), ("forward_backward", fwd_bwd)):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out[key + "_ms"] = a.elapsed_time(b) / reps
+    if B.check() != 0:
+        raise RuntimeError("device status after the adjoint runs")
+    cells = int(L.interior_cells)
+    return {"workload": "64^3 periodic as 8 patches of 32^3, FP64, fast wave + noise; 20 steps "
+                        "at fixed dt, checkpoint every 5; gradient of the L2 density misfit",
+            "steps": nsteps, "checkpoint_every": every, **out,
+            "backward_over_forward": out["forward_backward_ms"] / out["forward_ms"] - 1.0,
+            "forward_cell_updates_per_s": cells * nsteps / (out["forward_ms"] * 1e-3)}
 
 
 def _cpu_model():
@@ -431,6 +631,10 @@ def main():
     ap.add_argument("--fp32-only", action="store_true",
                     help="skip the FP64 run (profiling of the FP32 kernels)")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the host-resident streamed update")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint workload's forward / backward timing")
     ap.add_argument("--no-lts", action="store_true",
                     help="skip the local-time-stepping run")
     ap.add_argument("--lts-span", type=float, default=8.0,
@@ -489,6 +693,7 @@ def main():
         log(f"[bench] CPU baseline: oracle on {args.cpu_block}^3 patches")
         cpu = cpu_baseline(args.cpu_block)
         log(f"[bench] oracle {cpu['value']:.4e} cell-updates/s on {cpu['cores']} threads")
+        log(f"[bench] oracle {cpu['single_thread']['value']:.4e} cell-updates/s on 1 thread")
     r64.pop("bunch")
     torch.cuda.empty_cache()
     r32 = None
@@ -505,6 +710,26 @@ def main():
         batched = run_batched(args.batched_steps, 2)
         log(f"[bench] batched vs per-bunch {batched['speedup_vs_per_bunch']:.2f}x, "
             f"vs per-patch {batched['speedup_vs_per_patch']:.2f}x")
+
+    stream = None
+    if not args.no_stream and r32 is not None:
+        torch.cuda.empty_cache()
+        stream = run_stream(w, r32["tile"])
+        log(f"[bench] streamed from host: {stream['slots_3']['ms']:.1f} ms with 3 slots, "
+            f"{stream['slots_1']['ms']:.1f} ms with 1 ({stream['slots_3']['pcie_gbs']:.1f} GB/s "
+            f"over PCIe), max diff vs resident {stream['max_abs_diff_vs_resident']:.1e}")
+    adj = None
+    if not args.no_adjoint:
+        torch.cuda.empty_cache()
+        adj = run_adjoint(3)
+        log(f"[bench] adjoint workload: forward {adj['forward_ms']:.1f} ms, forward + backward "
+            f"{adj['forward_backward_ms']:.1f} ms")
+    if cpu is not None and not args.no_batched:
+        torch.cuda.empty_cache()
+        log("[bench] CPU baseline: oracle step of the uneven bunch")
+        cpu["uneven_bunch_step"] = cpu_baseline_uneven()
+        log(f"[bench] oracle {cpu['uneven_bunch_step']['value']:.4e} cell-updates/s on the uneven "
+            f"bunch")
 
     lts_res = None
     if not args.no_lts:
@@ -570,6 +795,8 @@ def main():
         },
         "batched": batched,
         "local_time_stepping": lts_res,
+        "adjoint": adj,
+        "host_streaming": stream,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
