@@ -139,6 +139,10 @@ mhd_status mhd_bunch_cfl(mhd_bunch* h, const void* U_dev, const double* dx_dev,
  *  5. for every ready patch: U_prev <- U_cur (its whole padded block), then U_cur's owned
  *     cells and faces <- U_new's, t_prev[p] = t[p], t[p] += dt[p] (exactly t_end when the
  *     step was clipped to it).
+ * With free steps (dt_quantum == 0) and a bunch processed in one chunk (no scratch cap) the
+ * launches of steps 2-5 run over device-compacted tables of the ready patches' entries
+ * (persistent grids), so a step costs in proportion to the patches that advance; with time
+ * levels (most patches advance together) they run over the full tables.
  * A ready patch whose step (given or its own CFL step) is not finite and > 0 gets dt[p] = 0,
  * stays where it is and raises a status bit that mhd_bunch_check reports as MHD_EINVAL.
  * On return U_cur holds every patch at its time t[p] (no buffers to swap).  Start with
@@ -158,6 +162,20 @@ mhd_status mhd_bunch_lts_step(mhd_bunch* h, void* U_cur, void* U_new, void* U_pr
  * without computing anything (its guards are not read and its state is not checked). */
 mhd_status mhd_bunch_update(mhd_bunch* h, const void* U_in, void* U_out, const double* dt_dev,
                             const double* dx_dev, hipStream_t stream);
+
+/* The update followed by the next step's time step, reduced in the update's own tiles
+ * (§2.2: each patch carries its own time step; the time-step rule of mhd_bunch_cfl): the same
+ * U_out as mhd_bunch_update, and dt_next[p] = the minimum over all patches of the time step
+ * that mhd_bunch_cfl(global != 0) computes on U_out after mhd_bunch_fill_guards(U_out, nbr).
+ * For the cell-centred field of a patch's last cells the update uses the upper faces as that
+ * exchange will leave them: at a face shared with a neighbour, the value the neighbour's update
+ * writes there, which the tile computes from the same edge EMFs (so dt must be the same for
+ * neighbouring patches, as in a globally stepped run); at a domain boundary (nbr entry -1), the
+ * last owned face.  Patches with dt[p] == 0 contribute nothing.  dt_next must not alias dt.
+ * Saves the separate time-step pass over the state. */
+mhd_status mhd_bunch_update_cfl(mhd_bunch* h, const void* U_in, void* U_out, const double* dt_dev,
+                                const double* dx_dev, const int32_t* nbr_dev, double* dt_next_dev,
+                                hipStream_t stream);
 
 /* ---- allocation-free update ----
  * For callers that cannot allocate device memory around the update (code under HIP graph
@@ -263,6 +281,19 @@ mhd_status mhd_bunch_graph_capture(mhd_bunch* h, int32_t nsteps, void* U_a, void
                                    double* dt_dev, const double* dx_dev, const int32_t* nbr_dev,
                                    int32_t dt_mode, hipStream_t stream);
 mhd_status mhd_bunch_graph_launch(mhd_bunch* h, hipStream_t stream);
+
+/* Captures `nsteps` local time steps (mhd_bunch_lts_step with these arguments, validated the
+ * same way) into the handle's HIP graph, replacing any earlier one; mhd_bunch_graph_launch
+ * runs them.  A bunch processed in one chunk (no max_scratch_bytes cap, or one that holds the
+ * whole bunch) and free steps (dt_quantum == 0) compacts its launch tables to the ready patches
+ * on the device in every step (as mhd_bunch_lts_step does), so each captured step does work in
+ * proportion to the patches that advance.  Steps after every
+ * patch reached t_end do nothing.  Buffers are bound by address. */
+mhd_status mhd_bunch_lts_graph_capture(mhd_bunch* h, int32_t nsteps, void* U_cur, void* U_new,
+                                       void* U_prev, double* t_dev, double* t_prev_dev,
+                                       double* dt_dev, const double* dt_fixed_dev,
+                                       const double* dx_dev, const int32_t* nbr_dev, double t_end,
+                                       double dt_quantum, hipStream_t stream);
 
 /* ---- bunches whose state stays in host memory (§2.4 "DISPATCH Integration": patches are
  * bunched on the host and sent to the GPU, three bunches active at once -- one being

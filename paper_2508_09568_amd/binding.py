@@ -79,6 +79,7 @@ _SIGS = {
     "mhd_bunch_cfl": (C.c_int, [_h, _v, _v, _v, C.c_int32, _st]),
     "mhd_bunch_update": (C.c_int, [_h, _v, _v, _v, _v, _st]),
     "mhd_bunch_update_static": (C.c_int, [_h, _v, _v, _v, _v, _st]),
+    "mhd_bunch_update_cfl": (C.c_int, [_h, _v, _v, _v, _v, _v, _v, _st]),
     "mhd_bunch_check": (C.c_int, [_h, _st]),
     "mhd_bunch_profile": (C.c_int, [_h, C.c_int32]),
     "mhd_bunch_profile_read": (C.c_int, [_h, C.c_int32, _dp, C.POINTER(C.c_int64)]),
@@ -97,6 +98,8 @@ _SIGS = {
     "mhd_bunch_lts_step": (C.c_int, [_h, _v, _v, _v, _v, _v, _v, _v, _v, _v, C.c_double,
                                      C.c_double, _st]),
     "mhd_bunch_graph_launch": (C.c_int, [_h, _st]),
+    "mhd_bunch_lts_graph_capture": (C.c_int, [_h, C.c_int32, _v, _v, _v, _v, _v, _v, _v, _v, _v,
+                                             C.c_double, C.c_double, _st]),
     "mhd_bunch_set_predictor": (C.c_int, [_h, C.c_int32]),
     "mhd_bunch_predictor": (C.c_int32, [_h]),
     "mhd_bunch_predictor_count": (C.c_int32, [_h]),
@@ -239,6 +242,18 @@ class Bunch:
         self._check_dx(dx)
         _ok(mhd_bunch_update(self._h, _ptr(U_in), _ptr(U_out), _ptr(dt), _ptr(dx), _stream(stream)),
             "mhd_bunch_update", self._h)
+
+    def update_cfl(self, U_in, U_out, dt, dx, nbr, dt_next, stream=None):
+        """The update, and in the same tiles the next step's global time step of U_out as the
+        guard exchange with nbr will leave it (written to every entry of dt_next)."""
+        self._check_state(U_in, "U_in")
+        self._check_state(U_out, "U_out")
+        self._check_dt(dt)
+        self._check_dt_named(dt_next, "dt_next")
+        self._check_dx(dx)
+        self._check_nbr(nbr)
+        _ok(mhd_bunch_update_cfl(self._h, _ptr(U_in), _ptr(U_out), _ptr(dt), _ptr(dx), _ptr(nbr),
+                                 _ptr(dt_next), _stream(stream)), "mhd_bunch_update_cfl", self._h)
 
     def update_static(self, U_in, U_out, dt, dx, stream=None):
         """The update with the library's static device scratch (allocates nothing; the bunch
@@ -394,6 +409,26 @@ class Bunch:
                                _ptr(dx), _ptr(nbr), float(t_end), float(dt_quantum),
                                _stream(stream)),
             "mhd_bunch_lts_step", self._h)
+
+    def lts_graph_capture(self, nsteps, U_cur, U_new, U_prev, t, t_prev, dt, dx, nbr, t_end,
+                          dt_fixed=None, dt_quantum=0.0, stream=None):
+        """Capture nsteps local time steps (arguments as lts_step) in the handle's HIP graph;
+        graph_launch runs them."""
+        for x, what in ((U_cur, "U_cur"), (U_new, "U_new"), (U_prev, "U_prev")):
+            self._check_state(x, what)
+        for x, what in ((t, "t"), (t_prev, "t_prev"), (dt, "dt")):
+            self._check_dt_named(x, what)
+        if dt_fixed is not None:
+            self._check_dt_named(dt_fixed, "dt_fixed")
+        self._check_dx(dx)
+        self._check_nbr(nbr)
+        self._graph_refs = (U_cur, U_new, U_prev, t, t_prev, dt, dt_fixed, dx, nbr)
+        _ok(mhd_bunch_lts_graph_capture(self._h, int(nsteps), _ptr(U_cur), _ptr(U_new),
+                                        _ptr(U_prev), _ptr(t), _ptr(t_prev), _ptr(dt),
+                                        None if dt_fixed is None else _ptr(dt_fixed), _ptr(dx),
+                                        _ptr(nbr), float(t_end), float(dt_quantum),
+                                        _stream(stream)),
+            "mhd_bunch_lts_graph_capture", self._h)
 
     def graph_launch(self, stream=None):
         _ok(mhd_bunch_graph_launch(self._h, _stream(stream)), "mhd_bunch_graph_launch", self._h)

@@ -59,6 +59,11 @@ __device__ __forceinline__ int remap_xcd(int b, int nb) {
 __device__ __forceinline__ int logical_block(int vb, int nb, int remap) {
   return remap ? remap_xcd(vb, nb) : vb;
 }
+// Table length of a launch: the host's count, or (tables compacted on the device, see
+// k_compact_scan) the count the device wrote; the grid is then a persistent one.
+__device__ __forceinline__ int table_count(int nb, const int* __restrict__ dcount) {
+  return dcount ? *dcount : nb;
+}
 
 __device__ __forceinline__ bool decode(const PatchDev& P, int kind, int g, int first, int& i, int& j,
                                        int& k) {
@@ -77,7 +82,9 @@ __global__ __launch_bounds__(BLK) void k_prim(const PatchDev* __restrict__ pt,
                                               const BoxBlock* __restrict__ blk,
                                               const T* __restrict__ U, T* __restrict__ S,
                                               const double* __restrict__ zdt, Consts<T> c, int g,
-                                              int* status, int nb, int remap) {
+                                              int* status, int nb0, int remap,
+                                              const int* __restrict__ dcount) {
+  const int nb = table_count(nb0, dcount);
   for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
     const BoxBlock b = blk[logical_block(vb, nb, remap)];
     if (zdt && zdt[b.patch] == 0.0) continue;
@@ -92,8 +99,9 @@ template <typename T>
 __global__ __launch_bounds__(BLK) void k_en(const PatchDev* __restrict__ pt,
                                             const BoxBlock* __restrict__ blk,
                                             const T* __restrict__ U, T* __restrict__ S,
-                                            const double* __restrict__ zdt, int g, int nb,
-                                            int remap) {
+                                            const double* __restrict__ zdt, int g, int nb0,
+                                            int remap, const int* __restrict__ dcount) {
+  const int nb = table_count(nb0, dcount);
   for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
     const BoxBlock b = blk[logical_block(vb, nb, remap)];
     if (zdt && zdt[b.patch] == 0.0) continue;
@@ -111,7 +119,8 @@ __global__ __launch_bounds__(BLK) void k_pred(const PatchDev* __restrict__ pt,
                                               const double* __restrict__ dt,
                                               const double* __restrict__ dx,
                                               const double* __restrict__ zdt, Consts<T> c, int g,
-                                              int nb, int remap) {
+                                              int nb0, int remap, const int* __restrict__ dcount) {
+  const int nb = table_count(nb0, dcount);
   for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
     const BoxBlock b = blk[logical_block(vb, nb, remap)];
     if (zdt && zdt[b.patch] == 0.0) continue;
@@ -141,9 +150,12 @@ __global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS))
 __attribute__((amdgpu_waves_per_eu(SolveWaves<T, TX, TY, TZ, FORM>::value))) void k_solve(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, const T* __restrict__ Uin,
     T* __restrict__ Uout, const T* __restrict__ S, const double* __restrict__ dt,
-    const double* __restrict__ dx, Consts<T> c, int g, int ntile, int remap, int copy_rest) {
+    const double* __restrict__ dx, Consts<T> c, int g, int ntile0, int remap, int copy_rest,
+    const int* __restrict__ dcount, unsigned long long* cfl_max, const int32_t* __restrict__ nbr) {
   __shared__ T lds[TileShape<TX, TY, TZ>::template Lds<FORM>::value];
+  __shared__ double red[TileShape<TX, TY, TZ>::THREADS / 64];
   DevX ex;
+  const int ntile = table_count(ntile0, dcount);
   for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
     const TileDev tl = tiles[logical_block(vb, ntile, remap)];
     const PatchDev& P = pt[tl.patch];
@@ -151,8 +163,19 @@ __attribute__((amdgpu_waves_per_eu(SolveWaves<T, TX, TY, TZ, FORM>::value))) voi
       if (copy_rest) copy_tile<TX, TY, TZ>(ex, P, g, tl, Uin, Uout);
       continue;
     }
-    solve_tile<T, TX, TY, TZ, FORM, EMF>(ex, lds, P, g, tl, Uin, Uout, S, dt[tl.patch],
-                                    dx + 3 * tl.patch, c);
+    double s = solve_tile<T, TX, TY, TZ, FORM, EMF>(ex, lds, P, g, tl, Uin, Uout, S, dt[tl.patch],
+                                                    dx + 3 * tl.patch, c, cfl_max ? nbr : nullptr,
+                                                    tl.patch);
+    if (cfl_max) {  // the tile's largest time-step sum -> the patch's slot (one atomic)
+      for (int o = 32; o > 0; o >>= 1) s = fmax(s, __shfl_xor(s, o));
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < TileShape<TX, TY, TZ>::THREADS / 64; ++w) m = fmax(m, red[w]);
+        atomicMax(cfl_max + tl.patch, (unsigned long long)__double_as_longlong(m));
+      }
+    }
     ex.sync();  // the next tile reuses the shared memory
   }
 }
@@ -172,10 +195,11 @@ __global__ __launch_bounds__((PredShape<PX, PY, PZ>::THREADS))
 __attribute__((amdgpu_waves_per_eu(PredWaves<T, PX, PY, PZ>::value))) void k_predict(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, const T* __restrict__ U,
     T* __restrict__ W, const double* __restrict__ dt, const double* __restrict__ dx, Consts<T> c,
-    int g, int* status, int ntile, int remap) {
+    int g, int* status, int ntile0, int remap, const int* __restrict__ dcount) {
   __shared__ T lds[PredShape<PX, PY, PZ>::LDS_ELEMS];
   DevX ex;
   int bad = 0;
+  const int ntile = table_count(ntile0, dcount);
   for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
     const TileDev tl = tiles[logical_block(vb, ntile, remap)];
     if (dt[tl.patch] == 0.0) continue;  // patch at rest: no predictor values needed
@@ -192,9 +216,10 @@ template <typename T, int TX, int TY, int TZ, int EMF>
 __global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS)) __attribute__((amdgpu_waves_per_eu(3)))
 void k_edges(
     const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, T* __restrict__ S,
-    const double* __restrict__ dt, const double* __restrict__ dx, Consts<T> c, int g, int ntile,
-    int remap) {
+    const double* __restrict__ dt, const double* __restrict__ dx, Consts<T> c, int g, int ntile0,
+    int remap, const int* __restrict__ dcount) {
   DevX ex;
+  const int ntile = table_count(ntile0, dcount);
   for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
     const TileDev tl = tiles[logical_block(vb, ntile, remap)];
     if (dt[tl.patch] == 0.0) continue;  // patch at rest: no EMFs needed
@@ -209,23 +234,28 @@ __global__ __launch_bounds__(BLK) void k_cfl(const PatchDev* __restrict__ pt,
                                              const BoxBlock* __restrict__ blk,
                                              const T* __restrict__ U, const double* __restrict__ dx,
                                              const int32_t* __restrict__ mask, Consts<T> c, int g,
-                                             unsigned long long* smax) {
-  const BoxBlock b = blk[blockIdx.x];
-  if (mask && !mask[b.patch]) return;  // whole work-group: patch not asked for (its dt: inf)
-  const PatchDev& P = pt[b.patch];
-  int i, j, k;
-  double s = 0.0;
-  if (decode(P, BOX_INTERIOR, g, b.first, i, j, k))
-    s = cfl_item(P, cell_of(P, i, j, k), U, dx + 3 * b.patch, c);
-  for (int o = 32; o > 0; o >>= 1) s = fmax(s, __shfl_xor(s, o));
+                                             unsigned long long* smax, int nb0,
+                                             const int* __restrict__ dcount) {
   __shared__ double red[BLK / 64];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = red[0];
-    for (int w = 1; w < BLK / 64; ++w) m = fmax(m, red[w]);
-    // s >= 0, so its IEEE bit pattern orders like the value
-    atomicMax(smax + b.patch, (unsigned long long)__double_as_longlong(m));
+  const int nb = table_count(nb0, dcount);
+  for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
+    const BoxBlock b = blk[vb];
+    if (mask && !mask[b.patch]) continue;  // whole work-group: patch not asked for (dt: inf)
+    const PatchDev& P = pt[b.patch];
+    int i, j, k;
+    double s = 0.0;
+    if (decode(P, BOX_INTERIOR, g, b.first, i, j, k))
+      s = cfl_item(P, cell_of(P, i, j, k), U, dx + 3 * b.patch, c);
+    for (int o = 32; o > 0; o >>= 1) s = fmax(s, __shfl_xor(s, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = red[0];
+      for (int w = 1; w < BLK / 64; ++w) m = fmax(m, red[w]);
+      // s >= 0, so its IEEE bit pattern orders like the value
+      atomicMax(smax + b.patch, (unsigned long long)__double_as_longlong(m));
+    }
+    __syncthreads();  // red is rewritten by the next block
   }
 }
 
@@ -292,15 +322,19 @@ __global__ __launch_bounds__(BLK) void k_guards_at(const PatchDev* __restrict__ 
                                                    const double* __restrict__ tprev,
                                                    const int32_t* __restrict__ nbr,
                                                    const int32_t* __restrict__ ready, int g,
-                                                   int np, int* status) {
-  const BoxBlock b = blk[blockIdx.x];
-  if (!ready[b.patch]) return;
-  const PatchDev& P = pt[b.patch];
-  const int q = b.first + (int)threadIdx.x;
-  if (q >= guard_count(P)) return;
-  int i, j, k;
-  guard_cell(P, g, q, i, j, k);
-  if (guard_item_at(pt, b.patch, g, i, j, k, U, Uprev, t, tprev, nbr, np)) atomicOr(status, 2);
+                                                   int np, int* status, int nb0,
+                                                   const int* __restrict__ dcount) {
+  const int nb = table_count(nb0, dcount);
+  for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
+    const BoxBlock b = blk[vb];
+    if (!ready[b.patch]) continue;
+    const PatchDev& P = pt[b.patch];
+    const int q = b.first + (int)threadIdx.x;
+    if (q >= guard_count(P)) continue;
+    int i, j, k;
+    guard_cell(P, g, q, i, j, k);
+    if (guard_item_at(pt, b.patch, g, i, j, k, U, Uprev, t, tprev, nbr, np)) atomicOr(status, 2);
+  }
 }
 
 // step of each patch: its own (or the given) step, rounded down to quantum x 2^k when a
@@ -337,18 +371,22 @@ template <typename T>
 __global__ __launch_bounds__(BLK) void k_lts_keep(const PatchDev* __restrict__ pt,
                                                   const BoxBlock* __restrict__ blk, T* U,
                                                   const T* __restrict__ Unew, T* __restrict__ Uprev,
-                                                  const int32_t* __restrict__ ready, int g) {
-  const BoxBlock b = blk[blockIdx.x];
-  if (!ready[b.patch]) return;
-  const PatchDev& P = pt[b.patch];
-  int x[3];
-  if (!decode(P, BOX_ALL, g, b.first, x[0], x[1], x[2])) return;
-  const int64_t cell = cell_of(P, x[0], x[1], x[2]);
-  const bool own = owned(P, g, x);
-  for (int m = 0; m < 8; ++m) {
-    const int64_t e = P.ubase + m * P.Nc + cell;
-    Uprev[e] = U[e];
-    if (own) U[e] = Unew[e];
+                                                  const int32_t* __restrict__ ready, int g,
+                                                  int nb0, const int* __restrict__ dcount) {
+  const int nb = table_count(nb0, dcount);
+  for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
+    const BoxBlock b = blk[vb];
+    if (!ready[b.patch]) continue;
+    const PatchDev& P = pt[b.patch];
+    int x[3];
+    if (!decode(P, BOX_ALL, g, b.first, x[0], x[1], x[2])) continue;
+    const int64_t cell = cell_of(P, x[0], x[1], x[2]);
+    const bool own = owned(P, g, x);
+    for (int m = 0; m < 8; ++m) {
+      const int64_t e = P.ubase + m * P.Nc + cell;
+      Uprev[e] = U[e];
+      if (own) U[e] = Unew[e];
+    }
   }
 }
 
@@ -363,6 +401,109 @@ __global__ __launch_bounds__(BLK) void k_lts_time(const int32_t* __restrict__ re
   const double tp = t[p];
   tprev[p] = tp;
   t[p] = dt[p] >= t_end - tp ? t_end : tp + dt[p];
+}
+
+// ------------------------------------------------- compaction of the launch tables
+// In a local time step only the ready patches work.  Every launch table (blocks or tiles)
+// lists its entries patch by patch, so first[p] .. first[p + 1] are patch p's entries; the
+// step copies the entries of the ready patches, in patch order, into compacted tables whose
+// lengths the device writes, and the kernels run persistent grids over them.
+constexpr int MAXKIND = 8;
+struct CompactArgs {
+  int nk;                              // tables compacted this step (<= MAXKIND)
+  const int32_t* first[MAXKIND];       // per table: first entry of every patch, [P + 1]
+  const uint64_t* src[MAXKIND];        // the full tables
+  uint64_t* dst[MAXKIND];              // their compacted copies
+  int words[MAXKIND];                  // 64-bit words per entry (BoxBlock 1, TileDev 2)
+  int32_t* pref;                       // [MAXKIND][P + 1]: first compacted entry per ready patch
+  int32_t* total;                      // [MAXKIND + 1]: entries per table, then the ready count
+  int32_t* list;                       // ready patches in order, [P]
+  int np;
+};
+
+// exclusive prefix sum over the work-group (a multiple of 64 threads, at most 1024); *total
+// receives the sum
+__device__ __forceinline__ int block_scan_excl(int v, int* sh, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int k = 0; k < nw; ++k) {
+      const int t = sh[k];
+      sh[k] = acc;
+      acc += t;
+    }
+    sh[nw] = acc;
+  }
+  __syncthreads();
+  const int r = sh[w] + x - v;
+  *total = sh[nw];
+  __syncthreads();  // sh is reused by the next call
+  return r;
+}
+
+// one work-group of 1024 threads: the ready list, then per table the prefix of the ready
+// patches' entry counts
+__global__ __launch_bounds__(1024) void k_compact_scan(const int32_t* __restrict__ ready,
+                                                       CompactArgs a) {
+  __shared__ int sh[17];
+  int nr = 0;
+  for (int p0 = 0; p0 < a.np; p0 += 1024) {
+    const int p = p0 + (int)threadIdx.x;
+    const int f = p < a.np ? (ready[p] != 0) : 0;
+    int tot;
+    const int r = nr + block_scan_excl(f, sh, &tot);
+    if (f) a.list[r] = p;
+    nr += tot;
+  }
+  #pragma unroll
+  for (int k = 0; k < MAXKIND; ++k) {
+    if (k >= a.nk) break;
+    const int32_t* first = a.first[k];
+    int32_t* pref = a.pref + (int64_t)k * (a.np + 1);
+    int acc = 0;
+    for (int r0 = 0; r0 < nr; r0 += 1024) {
+      const int r = r0 + (int)threadIdx.x;
+      int c = 0;
+      if (r < nr) {
+        const int p = a.list[r];
+        c = first[p + 1] - first[p];
+      }
+      int tot;
+      const int e = acc + block_scan_excl(c, sh, &tot);
+      if (r < nr) pref[r] = e;
+      acc += tot;
+    }
+    if (threadIdx.x == 0) a.total[k] = acc;
+  }
+  if (threadIdx.x == 0) a.total[MAXKIND] = nr;
+}
+
+// work-groups take ready patches in turn and copy their entries of every table
+__global__ __launch_bounds__(BLK) void k_compact_copy(CompactArgs a) {
+  const int nr = a.total[MAXKIND];
+  #pragma unroll
+  for (int k = 0; k < MAXKIND; ++k) {
+    if (k >= a.nk) break;
+    const int32_t* first = a.first[k];
+    const int32_t* pref = a.pref + (int64_t)k * (a.np + 1);
+    const uint64_t* src = a.src[k];
+    uint64_t* dst = a.dst[k];
+    const int w = a.words[k];
+    for (int r = blockIdx.x; r < nr; r += gridDim.x) {
+      const int p = a.list[r];
+      const int f0 = first[p], n = (first[p + 1] - f0) * w;
+      const uint64_t* sp = src + (int64_t)f0 * w;
+      uint64_t* dp = dst + (int64_t)pref[r] * w;
+      for (int i = threadIdx.x; i < n; i += BLK) dp[i] = sp[i];
+    }
+  }
 }
 
 // ------------------------------------------------------------------- adjoint kernels
@@ -596,6 +737,20 @@ struct mhd_bunch {
   size_t o_ptiles[MAXPSHAPE] = {0};
   int64_t scratch_elems = 0;
   size_t o_ready = 0;  // local time stepping: ready flag per patch (int32)
+  // Compacted launch tables of a local time step (bunches of one chunk): for every table its
+  // per-patch first entries (uploaded) and room for a compacted copy.  Table ids: block kind k
+  // -> k, solver tiles of shape k -> NBOX + k, predictor tiles of shape k -> NBOX + MAXSHAPE + k.
+  static constexpr int NTAB = NBOX + MAXSHAPE + MAXPSHAPE;
+  std::vector<int32_t> first[NTAB];
+  size_t o_first[NTAB] = {0}, o_ctab[NTAB] = {0}, o_pref = 0, o_total = 0, o_list = 0;
+  bool compact = false;     // launches read the compacted tables (inside a local time step)
+  // mhd_bunch_update_cfl: the solver tiles also reduce the next step's time-step sums
+  unsigned long long* cfl_next = nullptr;
+  const int32_t* cfl_nbr = nullptr;
+  int cslot[NTAB];          // slot of each table in the step's compaction, -1 if none
+  // table id -> pointer and device count of its compacted copy
+  const void* ctab(int id) const { return ws + o_ctab[id]; }
+  const int* ccount(int id) const { return (const int*)(ws + o_total) + cslot[id]; }
   bool copy_rest = true;  // update: copy patches at rest (false inside a local time step)
   size_t o_pt = 0, o_blk[NBOX] = {0}, o_tiles[MAXSHAPE] = {0}, o_smax = 0, o_status = 0,
          o_scratch = 0;
@@ -717,9 +872,10 @@ void set_shapes(mhd_bunch* h) {
 
 template <typename T, int X, int Y, int Z, int FORM, int EMF>
 void solve_launch(mhd_bunch* h, int nt, const TileDev* tl, const T* Uin, T* Uout, const T* S,
-                  const double* dt, const double* dx, const Consts<T>& c, hipStream_t s) {
+                  const double* dt, const double* dx, const Consts<T>& c, hipStream_t s,
+                  const int* dcount) {
   int grid = nt;
-  if (h->mode == 2) {
+  if (h->mode == 2 || dcount) {
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &occ, reinterpret_cast<const void*>(k_solve<T, X, Y, Z, FORM, EMF>),
@@ -728,15 +884,15 @@ void solve_launch(mhd_bunch* h, int nt, const TileDev* tl, const T* Uin, T* Uout
     grid = h->persistent_grid(nt, occ);
   }
   hipLaunchKernelGGL((k_solve<T, X, Y, Z, FORM, EMF>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0,
-                     s, h->d_pt(), tl, Uin, Uout, S, dt, dx, c, h->g, nt, h->mode >= 1,
-                     h->copy_rest ? 1 : 0);
+                     s, h->d_pt(), tl, Uin, Uout, S, dt, dx, c, h->g, nt, h->mode >= 1 || dcount,
+                     h->copy_rest ? 1 : 0, dcount, h->cfl_next, h->cfl_nbr);
 }
 
 template <typename T, int X, int Y, int Z, int EMF>
 void edges_launch(mhd_bunch* h, int nt, const TileDev* tl, T* S, const double* dt,
-                  const double* dx, const Consts<T>& c, hipStream_t s) {
+                  const double* dx, const Consts<T>& c, hipStream_t s, const int* dcount) {
   int grid = nt;
-  if (h->mode == 2) {
+  if (h->mode == 2 || dcount) {
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &occ, reinterpret_cast<const void*>(k_edges<T, X, Y, Z, EMF>), TileShape<X, Y, Z>::THREADS,
@@ -745,7 +901,7 @@ void edges_launch(mhd_bunch* h, int nt, const TileDev* tl, T* S, const double* d
     grid = h->persistent_grid(nt, occ);
   }
   hipLaunchKernelGGL((k_edges<T, X, Y, Z, EMF>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0, s,
-                     h->d_pt(), tl, S, dt, dx, c, h->g, nt, h->mode >= 1);
+                     h->d_pt(), tl, S, dt, dx, c, h->g, nt, h->mode >= 1 || dcount, dcount);
 }
 
 // edges = true: the owned-edge pass of solver form 2; else the solver tiles
@@ -756,16 +912,19 @@ void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uou
   const int k = h->shape;
   const TileCand tc = h->shapes[k];
   const int nt = ch.ntile[k];
-  const TileDev* tl = h->d_tiles(k) + ch.tile0[k];
+  const int id = NBOX + k;
+  const bool cmp = h->compact && h->cslot[id] >= 0;
+  const TileDev* tl = cmp ? (const TileDev*)h->ctab(id) : h->d_tiles(k) + ch.tile0[k];
+  const int* dc = cmp ? h->ccount(id) : nullptr;
 #define MHD_TRY_EMF(X, Y, Z, EMF)                                                             \
   if (edges)                                                                                  \
-    edges_launch<T, X, Y, Z, EMF>(h, nt, tl, S, dt, dx, c, s);                                \
+    edges_launch<T, X, Y, Z, EMF>(h, nt, tl, S, dt, dx, c, s, dc);                            \
   else if (h->split == 2)                                                                     \
-    solve_launch<T, X, Y, Z, 2, EMF>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                  \
+    solve_launch<T, X, Y, Z, 2, EMF>(h, nt, tl, Uin, Uout, S, dt, dx, c, s, dc);              \
   else if (h->split == 1)                                                                     \
-    solve_launch<T, X, Y, Z, 1, EMF>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);                  \
+    solve_launch<T, X, Y, Z, 1, EMF>(h, nt, tl, Uin, Uout, S, dt, dx, c, s, dc);              \
   else                                                                                        \
-    solve_launch<T, X, Y, Z, 0, EMF>(h, nt, tl, Uin, Uout, S, dt, dx, c, s);
+    solve_launch<T, X, Y, Z, 0, EMF>(h, nt, tl, Uin, Uout, S, dt, dx, c, s, dc);
 #define MHD_TRY(X, Y, Z)                                                                      \
   if (tc.x == X && tc.y == Y && tc.z == Z) {                                                  \
     if (h->emf == 1) {                                                                        \
@@ -801,11 +960,14 @@ mhd_status launch_update(mhd_bunch* h, const T* Uin, T* Uout, const double* dt, 
       const int pk = h->fused - 1;
       const TileCand pc = h->pshapes[pk];
       const int nt = ch.nptile[pk];
-      const TileDev* tl = h->d_ptiles(pk) + ch.ptile0[pk];
+      const int id = NBOX + MAXSHAPE + pk;
+      const bool cmp = h->compact && h->cslot[id] >= 0;
+      const TileDev* tl = cmp ? (const TileDev*)h->ctab(id) : h->d_ptiles(pk) + ch.ptile0[pk];
+      const int* dc = cmp ? h->ccount(id) : nullptr;
 #define MHD_PRED_LAUNCH(X, Y, Z)                                                                \
   if (pc.x == X && pc.y == Y && pc.z == Z) {                                                   \
     int grid = nt;                                                                             \
-    if (h->mode == 2) {                                                                        \
+    if (h->mode == 2 || dc) {                                                                  \
       int occ = 0;                                                                             \
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                        \
               &occ, reinterpret_cast<const void*>(k_predict<T, X, Y, Z>),                      \
@@ -814,33 +976,49 @@ mhd_status launch_update(mhd_bunch* h, const T* Uin, T* Uout, const double* dt, 
       grid = h->persistent_grid(nt, occ);                                                      \
     }                                                                                          \
     hipLaunchKernelGGL((k_predict<T, X, Y, Z>), dim3(grid), dim3(PredShape<X, Y, Z>::THREADS), 0, \
-                       s, h->d_pt(), tl, Uin, S, dt, dx, c, h->g, h->d_status(), nt, rm);      \
+                       s, h->d_pt(), tl, Uin, S, dt, dx, c, h->g, h->d_status(), nt, rm || dc, dc);  \
   }
       MHD_PRED_SHAPES(h->act, MHD_PRED_LAUNCH)
 #undef MHD_PRED_LAUNCH
       h->toc(s, MHD_KERNEL_PREDICT, t0);
     }
+    // staged predictor: the block tables of the chunk, or their compacted copies
+    auto stage = [&](int kind, const BoxBlock*& tb, int& grid, const int*& dc) {
+      const int nb = ch.nblk[kind];
+      const bool cmp = h->compact && h->cslot[kind] >= 0;
+      tb = cmp ? (const BoxBlock*)h->ctab(kind) : h->d_blk(kind) + ch.blk0[kind];
+      dc = cmp ? h->ccount(kind) : nullptr;
+      grid = cmp ? h->persistent_grid(nb, 2048 / BLK) : h->stage_grid(nb);
+      return nb;
+    };
     if (!h->fused && ch.nblk[BOX_PRIM]) {
-      const int nb = ch.nblk[BOX_PRIM];
+      const BoxBlock* tb;
+      int grid;
+      const int* dc;
+      const int nb = stage(BOX_PRIM, tb, grid, dc);
       t0 = h->tic(s);
-      hipLaunchKernelGGL(k_prim<T>, dim3(h->stage_grid(nb)), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_PRIM) + ch.blk0[BOX_PRIM], Uin, S, dt, c, h->g,
-                         h->d_status(), nb, rm);
+      hipLaunchKernelGGL(k_prim<T>, dim3(grid), dim3(BLK), 0, s, h->d_pt(), tb, Uin, S, dt, c,
+                         h->g, h->d_status(), nb, rm || dc, dc);
       h->toc(s, MHD_KERNEL_PRIM, t0);
     }
     if (!h->fused && ch.nblk[BOX_EN]) {
-      const int nb = ch.nblk[BOX_EN];
+      const BoxBlock* tb;
+      int grid;
+      const int* dc;
+      const int nb = stage(BOX_EN, tb, grid, dc);
       t0 = h->tic(s);
-      hipLaunchKernelGGL(k_en<T>, dim3(h->stage_grid(nb)), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_EN) + ch.blk0[BOX_EN], Uin, S, dt, h->g, nb, rm);
+      hipLaunchKernelGGL(k_en<T>, dim3(grid), dim3(BLK), 0, s, h->d_pt(), tb, Uin, S, dt, h->g,
+                         nb, rm || dc, dc);
       h->toc(s, MHD_KERNEL_EDGE_EMF_N, t0);
     }
     if (!h->fused && ch.nblk[BOX_PRED]) {
-      const int nb = ch.nblk[BOX_PRED];
+      const BoxBlock* tb;
+      int grid;
+      const int* dc;
+      const int nb = stage(BOX_PRED, tb, grid, dc);
       t0 = h->tic(s);
-      hipLaunchKernelGGL(k_pred<T>, dim3(h->stage_grid(nb)), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], Uin, S, dt, dx, dt, c, h->g, nb,
-                         rm);
+      hipLaunchKernelGGL(k_pred<T>, dim3(grid), dim3(BLK), 0, s, h->d_pt(), tb, Uin, S, dt, dx,
+                         dt, c, h->g, nb, rm || dc, dc);
       h->toc(s, MHD_KERNEL_PREDICT, t0);
     }
     if (h->split == 2 && ch.ntile[h->shape]) {
@@ -864,8 +1042,11 @@ mhd_status launch_cfl(mhd_bunch* h, const T* U, const double* dx, double* dt, in
   hipEvent_t t0 = h->tic(s);
   hipLaunchKernelGGL(k_zero_u64, dim3((h->P + 255) / 256), dim3(256), 0, s, h->d_smax(), h->P);
   const int nb = (int)h->blocks[BOX_INTERIOR].size();
-  hipLaunchKernelGGL(k_cfl<T>, dim3(nb), dim3(BLK), 0, s, h->d_pt(), h->d_blk(BOX_INTERIOR), U, dx,
-                     mask, c, h->g, h->d_smax());
+  const bool cmp = h->compact && h->cslot[BOX_INTERIOR] >= 0;
+  hipLaunchKernelGGL(k_cfl<T>, dim3(cmp ? h->persistent_grid(nb, 2048 / BLK) : nb), dim3(BLK), 0, s,
+                     h->d_pt(), cmp ? (const BoxBlock*)h->ctab(BOX_INTERIOR) : h->d_blk(BOX_INTERIOR),
+                     U, dx, mask, c, h->g, h->d_smax(), nb,
+                     cmp ? h->ccount(BOX_INTERIOR) : nullptr);
   hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(BLK), 0, s, h->P, (const unsigned long long*)h->d_smax(),
                      h->cfl, dt, global);
   h->toc(s, MHD_KERNEL_CFL, t0);
@@ -935,15 +1116,15 @@ mhd_status launch_adjoint(mhd_bunch* h, const T* U, const T* lam, T* lam_in, con
     if (ch.nblk[BOX_PRIM])
       hipLaunchKernelGGL(k_prim<T>, dim3(ch.nblk[BOX_PRIM]), dim3(BLK), 0, s, h->d_pt(),
                          h->d_blk(BOX_PRIM) + ch.blk0[BOX_PRIM], U, S, (const double*)nullptr, c,
-                         h->g, h->d_status(), ch.nblk[BOX_PRIM], 0);
+                         h->g, h->d_status(), ch.nblk[BOX_PRIM], 0, (const int*)nullptr);
     if (ch.nblk[BOX_EN])
       hipLaunchKernelGGL(k_en<T>, dim3(ch.nblk[BOX_EN]), dim3(BLK), 0, s, h->d_pt(),
                          h->d_blk(BOX_EN) + ch.blk0[BOX_EN], U, S, (const double*)nullptr, h->g,
-                         ch.nblk[BOX_EN], 0);
+                         ch.nblk[BOX_EN], 0, (const int*)nullptr);
     if (ch.nblk[BOX_PRED])
       hipLaunchKernelGGL(k_pred<T>, dim3(ch.nblk[BOX_PRED]), dim3(BLK), 0, s, h->d_pt(),
                          h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], U, S, dt, dx,
-                         (const double*)nullptr, c, h->g, ch.nblk[BOX_PRED], 0);
+                         (const double*)nullptr, c, h->g, ch.nblk[BOX_PRED], 0, (const int*)nullptr);
     // reverse sweep: predictor data, EMFs at t^n, primitives, padded input state
     if (ch.nblk[BOX_PRED])
       hipLaunchKernelGGL(k_adj_w<T>, dim3(ch.nblk[BOX_PRED], NW), dim3(BLK), 0, s, h->d_pt(),
@@ -976,30 +1157,76 @@ mhd_status launch_lts_step(mhd_bunch* h, T* Ucur, T* Unew, T* Uprev, double* t, 
   int32_t* ready = h->d_ready();
   hipLaunchKernelGGL(k_lts_ready, dim3(pg), dim3(BLK), 0, s, nbr, (const double*)t, t_end, ready,
                      h->P);
+  // With free steps few patches are ready at a time: with one chunk, every launch below then
+  // runs over the ready patches' entries only (the tables it reads are compacted on the device
+  // first, persistent grids).  With time levels (quantum > 0) patches advance in lock-step
+  // groups, most of the bunch at once, where the tuned full-table launches are faster.
+  const bool cmp = h->chunks.size() == 1 && !(quantum > 0.0);
+  if (cmp) {
+    CompactArgs a = {};
+    a.np = h->P;
+    auto add = [&](int id, int words) {
+      h->cslot[id] = a.nk;
+      a.first[a.nk] = (const int32_t*)(h->ws + h->o_first[id]);
+      a.src[a.nk] = (const uint64_t*)(id < NBOX ? (const void*)h->d_blk(id)
+                                     : id < NBOX + MAXSHAPE ? (const void*)h->d_tiles(id - NBOX)
+                                                            : (const void*)h->d_ptiles(id - NBOX - MAXSHAPE));
+      a.dst[a.nk] = (uint64_t*)(h->ws + h->o_ctab[id]);
+      a.words[a.nk] = words;
+      ++a.nk;
+    };
+    for (int id = 0; id < mhd_bunch::NTAB; ++id) h->cslot[id] = -1;
+    add(BOX_GUARD, 1);
+    add(BOX_ALL, 1);
+    if (!dt_fixed) add(BOX_INTERIOR, 1);
+    add(NBOX + h->shape, 2);
+    if (h->fused) {
+      add(NBOX + MAXSHAPE + h->fused - 1, 2);
+    } else {
+      add(BOX_PRIM, 1);
+      add(BOX_EN, 1);
+      add(BOX_PRED, 1);
+    }
+    a.pref = (int32_t*)(h->ws + h->o_pref);
+    a.total = (int32_t*)(h->ws + h->o_total);
+    a.list = (int32_t*)(h->ws + h->o_list);
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, (const int32_t*)ready, a);
+    hipLaunchKernelGGL(k_compact_copy, dim3(std::min(h->P, h->ncu * 4)), dim3(BLK), 0, s, a);
+    h->compact = true;
+  }
   const int ng = (int)h->blocks[BOX_GUARD].size();
   if (ng) {
     hipEvent_t t0 = h->tic(s);
-    hipLaunchKernelGGL(k_guards_at<T>, dim3(ng), dim3(BLK), 0, s, h->d_pt(), h->d_blk(BOX_GUARD),
-                       Ucur, (const T*)Uprev, (const double*)t, (const double*)tprev, nbr,
-                       (const int32_t*)ready, h->g, h->P, h->d_status());
+    hipLaunchKernelGGL(k_guards_at<T>, dim3(cmp ? h->persistent_grid(ng, 2048 / BLK) : ng),
+                       dim3(BLK), 0, s, h->d_pt(),
+                       cmp ? (const BoxBlock*)h->ctab(BOX_GUARD) : h->d_blk(BOX_GUARD), Ucur,
+                       (const T*)Uprev, (const double*)t, (const double*)tprev, nbr,
+                       (const int32_t*)ready, h->g, h->P, h->d_status(), ng,
+                       cmp ? h->ccount(BOX_GUARD) : nullptr);
     h->toc(s, MHD_KERNEL_GUARDS, t0);
   }
-  if (!dt_fixed) {
-    const mhd_status st = launch_cfl<T>(h, (const T*)Ucur, dx, dt, 0, s, ready);
-    if (st != MHD_OK) return st;
+  mhd_status st = MHD_OK;
+  if (!dt_fixed) st = launch_cfl<T>(h, (const T*)Ucur, dx, dt, 0, s, ready);
+  if (st == MHD_OK) {
+    hipLaunchKernelGGL(k_lts_dt, dim3(pg), dim3(BLK), 0, s, ready, (const double*)t,
+                       t_end, quantum, dt_fixed ? dt_fixed : (const double*)dt, dt, h->P,
+                       h->d_status());
+    h->copy_rest = false;  // U_new is scratch: only the ready patches' results are kept
+    st = launch_update<T>(h, (const T*)Ucur, Unew, dt, dx, s, (T*)h->d_scratch());
+    h->copy_rest = true;
   }
-  hipLaunchKernelGGL(k_lts_dt, dim3(pg), dim3(BLK), 0, s, ready, (const double*)t,
-                     t_end, quantum, dt_fixed ? dt_fixed : (const double*)dt, dt, h->P,
-                     h->d_status());
-  h->copy_rest = false;  // U_new is scratch: only the ready patches' results are kept
-  const mhd_status st = launch_update<T>(h, (const T*)Ucur, Unew, dt, dx, s, (T*)h->d_scratch());
-  h->copy_rest = true;
+  if (st == MHD_OK) {
+    const int na = (int)h->blocks[BOX_ALL].size();
+    hipLaunchKernelGGL(k_lts_keep<T>, dim3(cmp ? h->persistent_grid(na, 2048 / BLK) : na),
+                       dim3(BLK), 0, s, h->d_pt(),
+                       cmp ? (const BoxBlock*)h->ctab(BOX_ALL) : h->d_blk(BOX_ALL), Ucur,
+                       (const T*)Unew, Uprev, (const int32_t*)ready, h->g, na,
+                       cmp ? h->ccount(BOX_ALL) : nullptr);
+    hipLaunchKernelGGL(k_lts_time, dim3(pg), dim3(BLK), 0, s, (const int32_t*)ready, t, tprev,
+                       (const double*)dt, t_end, h->P);
+  }
+  h->compact = false;
   if (st != MHD_OK) return st;
-  const int na = (int)h->blocks[BOX_ALL].size();
-  hipLaunchKernelGGL(k_lts_keep<T>, dim3(na), dim3(BLK), 0, s, h->d_pt(), h->d_blk(BOX_ALL), Ucur,
-                     (const T*)Unew, Uprev, (const int32_t*)ready, h->g);
-  hipLaunchKernelGGL(k_lts_time, dim3(pg), dim3(BLK), 0, s, (const int32_t*)ready, t, tprev,
-                     (const double*)dt, t_end, h->P);
   return h->hip_ok(hipGetLastError(), "launch local time step") ? MHD_OK : MHD_EDEVICE;
 }
 
@@ -1218,6 +1445,17 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
     }
     ch.nblk_all = (int)h->blocks[BOX_ALL].size() - ch.blk0_all;
   }
+  // per-patch first entry of every launch table (each lists its entries patch by patch)
+  auto firsts = [&](std::vector<int32_t>& f, auto const& tab) {
+    f.assign(h->P + 1, 0);
+    std::vector<int32_t> cnt(h->P, 0);
+    for (const auto& e : tab) cnt[e.patch]++;
+    for (int p = 0; p < h->P; ++p) f[p + 1] = f[p] + cnt[p];
+  };
+  for (int k = 0; k < NBOX; ++k) firsts(h->first[k], h->blocks[k]);
+  for (int k = 0; k < h->nshape; ++k) firsts(h->first[NBOX + k], h->tiles[k]);
+  for (int k = 0; k < h->npshape; ++k) firsts(h->first[NBOX + MAXSHAPE + k], h->ptiles[k]);
+  for (int id = 0; id < mhd_bunch::NTAB; ++id) h->cslot[id] = -1;
   // workspace layout
   size_t o = 0;
   h->o_pt = o;
@@ -1240,6 +1478,27 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
   o = align256(o + sizeof(unsigned long long));
   h->o_ready = o;
   o = align256(o + sizeof(int32_t) * h->P);
+  // compaction of a local time step: first entries, compacted copies, prefix sums, counts
+  {
+    auto entry_bytes = [&](int id) -> size_t {
+      if (id < NBOX) return sizeof(BoxBlock) * h->blocks[id].size();
+      if (id < NBOX + MAXSHAPE) return sizeof(TileDev) * h->tiles[id - NBOX].size();
+      return sizeof(TileDev) * h->ptiles[id - NBOX - MAXSHAPE].size();
+    };
+    for (int id = 0; id < mhd_bunch::NTAB; ++id) {
+      if (h->first[id].empty()) continue;
+      h->o_first[id] = o;
+      o = align256(o + sizeof(int32_t) * h->first[id].size());
+      h->o_ctab[id] = o;
+      o = align256(o + std::max<size_t>(16, entry_bytes(id)));
+    }
+    h->o_pref = o;
+    o = align256(o + sizeof(int32_t) * (size_t)MAXKIND * (h->P + 1));
+    h->o_total = o;
+    o = align256(o + sizeof(int32_t) * (MAXKIND + 1));
+    h->o_list = o;
+    o = align256(o + sizeof(int32_t) * h->P);
+  }
   h->o_scratch = o;
   o = align256(o + (size_t)h->scratch_elems * esz);
   h->ws_bytes = o;
@@ -1288,6 +1547,11 @@ mhd_status mhd_bunch_bind(mhd_bunch* h, void* ws, hipStream_t s) {
       ok = h->hip_ok(hipMemcpyAsync(h->ws + h->o_tiles[k], h->tiles[k].data(),
                                     sizeof(TileDev) * h->tiles[k].size(), hipMemcpyHostToDevice, s),
                      "upload tile table");
+  for (int id = 0; id < mhd_bunch::NTAB && ok; ++id)
+    if (!h->first[id].empty())
+      ok = h->hip_ok(hipMemcpyAsync(h->ws + h->o_first[id], h->first[id].data(),
+                                    sizeof(int32_t) * h->first[id].size(), hipMemcpyHostToDevice, s),
+                     "upload table index");
   if (ok) {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, (unsigned long long*)(h->ws + h->o_status), 1);
     ok = h->hip_ok(hipGetLastError(), "clear status word");
@@ -1396,6 +1660,36 @@ mhd_status mhd_bunch_update(mhd_bunch* h, const void* Uin, void* Uout, const dou
                                               (double*)h->d_scratch())
                       : launch_update<float>(h, (const float*)Uin, (float*)Uout, dt, dx, s,
                                              (float*)h->d_scratch());
+}
+
+mhd_status mhd_bunch_update_cfl(mhd_bunch* h, const void* Uin, void* Uout, const double* dt,
+                                const double* dx, const int32_t* nbr, double* dt_next,
+                                hipStream_t s) {
+  if (!h || !Uin || !Uout || !dt || !dx || !nbr || !dt_next || Uin == Uout ||
+      dt_next == dt)
+    return MHD_EINVAL;
+  if (!h->bound) return MHD_ESTATE;
+  const size_t bytes = (size_t)h->state_elems * h->prec;
+  const char *a = (const char*)Uin, *b = (const char*)Uout;
+  if (a < b + bytes && b < a + bytes) return MHD_EINVAL;
+  hipEvent_t t0 = h->tic(s);
+  hipLaunchKernelGGL(k_zero_u64, dim3((h->P + 255) / 256), dim3(256), 0, s, h->d_smax(), h->P);
+  h->toc(s, MHD_KERNEL_CFL, t0);
+  h->cfl_next = h->d_smax();
+  h->cfl_nbr = nbr;
+  const mhd_status st =
+      h->prec == 8 ? launch_update<double>(h, (const double*)Uin, (double*)Uout, dt, dx, s,
+                                           (double*)h->d_scratch())
+                   : launch_update<float>(h, (const float*)Uin, (float*)Uout, dt, dx, s,
+                                          (float*)h->d_scratch());
+  h->cfl_next = nullptr;
+  h->cfl_nbr = nullptr;
+  if (st != MHD_OK) return st;
+  t0 = h->tic(s);
+  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(BLK), 0, s, h->P,
+                     (const unsigned long long*)h->d_smax(), h->cfl, dt_next, 1);
+  h->toc(s, MHD_KERNEL_CFL, t0);
+  return h->hip_ok(hipGetLastError(), "launch update with time step") ? MHD_OK : MHD_EDEVICE;
 }
 
 mhd_status mhd_bunch_update_static(mhd_bunch* h, const void* Uin, void* Uout, const double* dt,
@@ -1791,6 +2085,46 @@ mhd_status mhd_stream_check(mhd_stream* S, hipStream_t s) {
 }
 
 const char* mhd_stream_last_error(const mhd_stream* S) { return S ? S->last_error : "null handle"; }
+
+mhd_status mhd_bunch_lts_graph_capture(mhd_bunch* h, int32_t nsteps, void* U_cur, void* U_new,
+                                       void* U_prev, double* t, double* t_prev, double* dt,
+                                       const double* dt_fixed, const double* dx,
+                                       const int32_t* nbr, double t_end, double dt_quantum,
+                                       hipStream_t s) {
+  (void)s;
+  if (!h || nsteps < 1) return MHD_EINVAL;
+  if (!h->bound) return MHD_ESTATE;
+  h->drop_graph();
+  hipStream_t cs = nullptr;
+  if (!h->hip_ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream"))
+    return MHD_EDEVICE;
+  const bool prof = h->prof;
+  h->prof = false;
+  mhd_status st = MHD_OK;
+  if (!h->hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture")) {
+    st = MHD_EDEVICE;
+  } else {
+    for (int k = 0; k < nsteps && st == MHD_OK; ++k)
+      st = mhd_bunch_lts_step(h, U_cur, U_new, U_prev, t, t_prev, dt, dt_fixed, dx, nbr, t_end,
+                              dt_quantum, cs);
+    hipGraph_t g = nullptr;
+    const bool ended = h->hip_ok(hipStreamEndCapture(cs, &g), "end capture");
+    if (st == MHD_OK && !ended) st = MHD_EDEVICE;
+    if (st == MHD_OK) {
+      h->graph = g;
+      if (!h->hip_ok(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0), "instantiate graph")) {
+        h->gexec = nullptr;
+        st = MHD_EDEVICE;
+      }
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  h->prof = prof;
+  (void)hipStreamDestroy(cs);
+  if (st != MHD_OK) h->drop_graph();
+  return st;
+}
 
 mhd_status mhd_bunch_graph_launch(mhd_bunch* h, hipStream_t s) {
   if (!h) return MHD_EINVAL;

@@ -595,19 +595,19 @@ __host__ __device__ __forceinline__ T edge_emf_item(const PatchDev& P, int g, in
 }
 
 // -------------------------------------------------------------- time step
-// sum over active directions of (|u_d| + c_f,d) / dx_d at interior cell `cell`
+// sum over active directions of (|u_d| + c_f,d) / dx_d of a cell with density r, momentum
+// m, energy e and the face fields bl (lower faces) and bu (upper faces)
 template <typename T>
-__host__ __device__ __forceinline__ double cfl_item(const PatchDev& P, int64_t cell, const T* U,
-                                                    const double* dxp, const Consts<T>& c) {
-  const int64_t Nc = P.Nc;
-  const T* u = U + P.ubase;
-  T rho = u[cell];
+__host__ __device__ __forceinline__ double cfl_point(const PatchDev& P, T r, const T m[3], T e,
+                                                     const T bl[3], const T bu[3],
+                                                     const double* dxp, const Consts<T>& c) {
+  T rho = r;
   if (rho < c.rho_floor) rho = c.rho_floor;
   const T ir = m_rcp(rho);
-  const T v[3] = {u[Nc + cell] * ir, u[2 * Nc + cell] * ir, u[3 * Nc + cell] * ir};
+  const T v[3] = {m[0] * ir, m[1] * ir, m[2] * ir};
   T B[3];
-  for (int d = 0; d < 3; ++d) B[d] = T(0.5) * (u[(5 + d) * Nc + cell] + u[(5 + d) * Nc + cell + P.off[d]]);
-  T p = c.gm1 * (u[4 * Nc + cell] - T(0.5) * rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) -
+  for (int d = 0; d < 3; ++d) B[d] = T(0.5) * (bl[d] + bu[d]);
+  T p = c.gm1 * (e - T(0.5) * rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) -
                  T(0.5) * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]));
   if (p < c.p_floor) p = c.p_floor;
   double s = 0.0;
@@ -617,6 +617,21 @@ __host__ __device__ __forceinline__ double cfl_item(const PatchDev& P, int64_t c
     s += (double)(m_abs(v[d]) + cf) / dxp[d];
   }
   return s;
+}
+
+// the same at interior cell `cell` of the state U
+template <typename T>
+__host__ __device__ __forceinline__ double cfl_item(const PatchDev& P, int64_t cell, const T* U,
+                                                    const double* dxp, const Consts<T>& c) {
+  const int64_t Nc = P.Nc;
+  const T* u = U + P.ubase;
+  const T m[3] = {u[Nc + cell], u[2 * Nc + cell], u[3 * Nc + cell]};
+  T bl[3], bu[3];
+  for (int d = 0; d < 3; ++d) {
+    bl[d] = u[(5 + d) * Nc + cell];
+    bu[d] = u[(5 + d) * Nc + cell + P.off[d]];
+  }
+  return cfl_point(P, u[cell], m, u[4 * Nc + cell], bl, bu, dxp, c);
 }
 
 // ------------------------------------------------------------------ guard fill
@@ -1072,11 +1087,19 @@ __host__ __device__ __forceinline__ void copy_tile(X& ex, const PatchDev& P, int
 // edge by a FORM 3 pass into the scratch slots of the time-n EMFs (P.sbase + (8 + e) Nc);
 // FORM 3: that pass -- the edges the tile owns (its cells' lower edges, plus the upper layer
 // where the tile ends the patch), written to the scratch, no update.
+// With nbr != nullptr the tile also returns the largest sum over directions of
+// (|u_d| + c_f,d) / dx_d of its updated cells (the time-step rule) as the state will be after
+// the guard exchange with the neighbour table nbr: the upper face of a cell is the face the
+// next cell's update writes, which the tile computes from its edge EMFs -- at a face shared
+// with a neighbour patch it is the value that patch's update writes there (the same EMFs,
+// the same dt); at a domain boundary (nbr entry -1) the exchange copies the last owned face.
+// Otherwise it returns 0.
 template <typename T, int TX, int TY, int TZ, int FORM, int EMF, class X>
-__host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDev& P, int g,
+__host__ __device__ __forceinline__ double solve_tile(X& ex, T* lds, const PatchDev& P, int g,
                                                     const TileDev& tl, const T* Uin, T* Uout,
                                                     const T* Win, double dt, const double* dxp,
-                                                    const Consts<T>& c) {
+                                                    const Consts<T>& c,
+                                                    const int32_t* nbr = nullptr, int patch = 0) {
   using SH = TileShape<TX, TY, TZ>;
   T* fx = lds;
   T* fy = fx + 5 * SH::NFX;
@@ -1123,6 +1146,16 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
   const T* u = Uin + P.ubase;
   T* uo = Uout + P.ubase;
   const LdRel<T> wa{Win + P.wbase};
+  // time step of the next step: per direction, whether the tile's last cells sit at a domain
+  // boundary (their upper face is then the exchange's copy of the last owned face)
+  const bool cfl = nbr != nullptr;
+  bool obnd[3] = {false, false, false};
+  if (cfl) {
+    obnd[0] = ax && tl.x0 + tx == P.n[0] && nbr[27 * patch + 14] < 0;
+    obnd[1] = ay && tl.y0 + ty == P.n[1] && nbr[27 * patch + 16] < 0;
+    obnd[2] = az && tl.z0 + tz == P.n[2] && nbr[27 * patch + 22] < 0;
+  }
+  double smx = 0.0;
 
   for (int phase = 0; phase < (SPLIT ? 2 : 1); ++phase) {
     if (EDGES) {
@@ -1149,7 +1182,7 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         else
           eo[0] = edge_emf_item<EMF>(P, g, e, i0 + lx, j0 + ly, k0 + lz, Win, c);
       }
-      return;
+      return 0.0;
     }
     const int ibeg = SPLIT && phase == 1 ? B3 : 0;
     const int iend = (SPLIT && phase == 0) || EXT ? B3 : B6;
@@ -1210,6 +1243,7 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
     for (int it = tid; it < ncell; it += nth) {
       const int lx = it % tx, ly = (it / tx) % ty, lz = it / (tx * ty);
       const int64_t cell = cell_of(P, i0 + lx, j0 + ly, k0 + lz);
+      T hn[5];  // the cell's new density, momentum, energy
       if (!SPLIT || phase == 0) {
         const int fxl = lx + (TX + 1) * (ly + TY * lz), fyl = lx + TX * (ly + (TY + 1) * lz),
                   fzl = lx + TX * (ly + TY * lz);
@@ -1219,8 +1253,12 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
           if (ay) v = v - dtdx[1] * (fy[m * SH::NFY + fyl + TX] - fy[m * SH::NFY + fyl]);
           if (az) v = v - dtdx[2] * (fz[m * SH::NFZ + fzl + TX * TY] - fz[m * SH::NFZ + fzl]);
           uo[m * Nc + cell] = v;
+          hn[m] = v;
         }
+      } else if (cfl) {
+        for (int m = 0; m < 5; ++m) hn[m] = uo[m * Nc + cell];  // written by this thread in phase 0
       }
+      T bl[3], bu[3];  // new lower and upper faces (time step of the next step)
       if (EXT) {
         const int64_t ox = P.off[0], oy = P.off[1], oz = P.off[2];
         const T* E0 = eg;
@@ -1236,6 +1274,18 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         uo[5 * Nc + cell] = bx;
         uo[6 * Nc + cell] = by;
         uo[7 * Nc + cell] = bz;
+        if (cfl) {
+          bl[0] = bx; bl[1] = by; bl[2] = bz;
+          const int64_t cx = cell + ox, cy = cell + oy, cz = cell + oz;
+          T ux = u[5 * Nc + cx], uy = u[6 * Nc + cy], uz = u[7 * Nc + cz];
+          if (ay) ux = ux + dtdx[1] * (E2[cx + oy] - E2[cx]);
+          if (az) ux = ux - dtdx[2] * (E1[cx + oz] - E1[cx]);
+          if (az) uy = uy + dtdx[2] * (E0[cy + oz] - E0[cy]);
+          if (ax) uy = uy - dtdx[0] * (E2[cy + ox] - E2[cy]);
+          if (ax) uz = uz + dtdx[0] * (E1[cz + ox] - E1[cz]);
+          if (ay) uz = uz - dtdx[1] * (E0[cz + oy] - E0[cz]);
+          bu[0] = ux; bu[1] = uy; bu[2] = uz;
+        }
       } else if (!SPLIT || phase == 1) {
         // edge arrays: ez (TX+1)x(TY+1)xTZ, ex TXx(TY+1)x(TZ+1), ey (TX+1)xTYx(TZ+1)
         const int zl = lx + (TX + 1) * (ly + (TY + 1) * lz);
@@ -1251,10 +1301,37 @@ __host__ __device__ __forceinline__ void solve_tile(X& ex, T* lds, const PatchDe
         uo[5 * Nc + cell] = bx;
         uo[6 * Nc + cell] = by;
         uo[7 * Nc + cell] = bz;
+        if (cfl) {
+          bl[0] = bx; bl[1] = by; bl[2] = bz;
+          // the same formulas one face up: x at (lx + 1), y at (ly + 1), z at (lz + 1)
+          const int zx = zl + 1, yx = yl + 1;
+          const int xy = xl + TX, zy = zl + (TX + 1);
+          const int yz = yl + (TX + 1) * TY, xz = xl + TX * (TY + 1);
+          T ux = u[5 * Nc + cell + P.off[0]], uy = u[6 * Nc + cell + P.off[1]],
+            uz = u[7 * Nc + cell + P.off[2]];
+          if (ay) ux = ux + dtdx[1] * (ez[zx + (TX + 1)] - ez[zx]);
+          if (az) ux = ux - dtdx[2] * (ey[yx + (TX + 1) * TY] - ey[yx]);
+          if (az) uy = uy + dtdx[2] * (exx[xy + TX * (TY + 1)] - exx[xy]);
+          if (ax) uy = uy - dtdx[0] * (ez[zy + 1] - ez[zy]);
+          if (ax) uz = uz + dtdx[0] * (ey[yz + 1] - ey[yz]);
+          if (ay) uz = uz - dtdx[1] * (exx[xz + TX] - exx[xz]);
+          bu[0] = ux; bu[1] = uy; bu[2] = uz;
+        }
+      }
+      if (cfl && (!SPLIT || phase == 1)) {
+        const bool last[3] = {lx == tx - 1, ly == ty - 1, lz == tz - 1};
+        for (int d = 0; d < 3; ++d) {
+          if (!fact[d]) bu[d] = bl[d];                     // collapsed: one face
+          else if (obnd[d] && last[d]) bu[d] = bl[d];      // exchange copies the last owned face
+        }
+        const T mn[3] = {hn[1], hn[2], hn[3]};
+        const double sc = cfl_point(P, hn[0], mn, hn[4], bl, bu, dxp, c);
+        smx = smx > sc ? smx : sc;
       }
     }
     if (SPLIT && phase == 0) ex.sync();  // the edge phase overwrites the fluxes
   }
+  return smx;
 }
 
 }  // namespace mhd

@@ -7,6 +7,33 @@ from __future__ import annotations
 import torch
 
 
+def run_graph(bunch, U, dx, nbr, t_end, dt_fixed=None, dt_quantum=0.0, steps_per_graph=16,
+              max_steps=1_000_000):
+    """The same run with `steps_per_graph` local time steps captured in one HIP graph
+    (mhd_bunch_lts_graph_capture), launched until every patch has reached t_end; the host reads
+    the device status and the times after each launch.  Same results as run(), bit for bit.
+    Returns (U at t_end, t, steps launched)."""
+    from .binding import MhdError
+    P = bunch.P
+    dev = U.device
+    Ua, Ub, Up = U.clone(), torch.empty_like(U), U.clone()
+    t = torch.zeros(P, dtype=torch.float64, device=dev)
+    tp = torch.zeros(P, dtype=torch.float64, device=dev)
+    dt = torch.zeros(P, dtype=torch.float64, device=dev)
+    bunch.lts_graph_capture(steps_per_graph, Ua, Ub, Up, t, tp, dt, dx, nbr, t_end,
+                            dt_fixed=dt_fixed, dt_quantum=dt_quantum)
+    n = 0
+    while n < max_steps:
+        bunch.graph_launch()
+        n += steps_per_graph
+        rc = bunch.check()
+        if rc != 0:
+            raise MhdError(rc, "lts.run_graph: device status after step %d" % n)
+        if bool((t >= t_end).all()):
+            return Ua, t, n
+    raise RuntimeError("lts.run_graph: step limit reached")
+
+
 def run(bunch, U, dx, nbr, t_end, dt_fixed=None, dt_quantum=0.0, check_every=16,
         max_steps=1_000_000):
     """Advance the state tensor U (guards filled or not) to t_end; dt_quantum > 0 rounds every

@@ -275,3 +275,34 @@ def test_bad_given_step_stops_the_patch_and_is_reported():
     assert np.all(dth[~bad] == 1e-4) and np.all(th[~bad] == 1e-4)
     for p in np.nonzero(bad)[0]:
         assert np.array_equal(L.interior(got, p), L.interior(U, p))
+
+
+@pytest.mark.parametrize("case", ["periodic", "outflow_corner"])
+def test_compacted_captured_and_chunked_runs_agree_bitwise(case):
+    """The same local-time-stepping run (each patch at its own CFL step) three ways: one
+    chunk, so every step compacts its launch tables to the ready patches (eager calls); the
+    same with the steps captured in HIP graphs; and a bunch processed in several scratch
+    chunks, whose steps launch over every patch.  All give the same bits and times."""
+    import torch
+    from paper_2508_09568_amd import lts
+    log(f"[gpu] lts compacted / captured / chunked, case {case}")
+    w, U = _turb3d(case)
+    L = w.layout
+    import oracle
+    prm = oracle.Params(gamma=w.gamma, cfl=w.cfl)
+    own = oracle.cfl_many(U, L.dims, L.g, w.dx, prm)
+    t_end = 6 * float(own.min())
+    Ud, dxd, nbd = dev(U), dev(w.dx), dev(w.nbr.astype(np.int32))
+    B1 = make_bunch(L, w.gamma)
+    Ua, ta, na, ca = lts.run(B1, Ud, dxd, nbd, t_end, check_every=1)
+    assert B1.check() == 0
+    Ug, tg, ng = lts.run_graph(B1, Ud, dxd, nbd, t_end, steps_per_graph=4)
+    assert B1.check() == 0
+    per = int(8 * np.prod(L.dims[0] + 2 * L.g)) * 8 * 11   # scratch of about one patch
+    Bc = make_bunch(L, w.gamma, max_scratch_bytes=2 * per)
+    Uc, tc, nc, cc = lts.run(Bc, Ud, dxd, nbd, t_end, check_every=1)
+    assert Bc.check() == 0
+    log(f"    {na} steps, updates per patch {int(ca.min())}..{int(ca.max())}; graph launched {ng}")
+    assert int(ca.min()) < int(ca.max())
+    assert torch.equal(ta, tg) and torch.equal(ta, tc) and torch.equal(ca, cc) and na == nc
+    assert torch.equal(Ua, Ug) and torch.equal(Ua, Uc)
