@@ -359,7 +359,7 @@ def run_lts(w, tile, t_mult):
     for key, q in (("lts", 0.0), ("lts_levels", quantum)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, tl, nl, cnt = lts.run(B, U, dx, nbr, t_end, dt_quantum=q, check_every=8)
+        Ul, tl, nl, cnt = lts.run(B, U, dx, nbr, t_end, dt_quantum=q, check_every=8)
         torch.cuda.synchronize()
         wall_l = time.perf_counter() - t0
         if B.check() != 0:
@@ -370,6 +370,17 @@ def run_lts(w, tile, t_mult):
                     "cell_updates": upd_l, "ms": 1e3 * wall_l,
                     "cell_updates_per_s": upd_l / wall_l,
                     "work_ratio": upd_l / upd_g, "time_ratio": wall_l / wall_g}
+        # the same run with 16 steps per captured graph (same schedule, same bits)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Ug, tg, ng = lts.run_graph(B, U, dx, nbr, t_end, dt_quantum=q, steps_per_graph=16)
+        torch.cuda.synchronize()
+        wall_c = time.perf_counter() - t0
+        res[key]["graph"] = {"steps_launched": ng, "ms": 1e3 * wall_c,
+                             "cell_updates_per_s": upd_l / wall_c,
+                             "time_ratio": wall_c / wall_g,
+                             "same_bits_as_eager": bool(torch.equal(Ug, Ul) and torch.equal(tg, tl))}
+        del Ug, Ul
     return res
 
 
@@ -741,6 +752,9 @@ def main():
                 f"ms, work {r['work_ratio']:.2f}x and time {r['time_ratio']:.2f}x of global "
                 f"stepping ({lts_res['global']['steps']} steps, "
                 f"{lts_res['global']['ms']:.1f} ms)")
+            log(f"[bench] {key} in graphs of 16 steps: {r['graph']['ms']:.1f} ms, time "
+                f"{r['graph']['time_ratio']:.2f}x of global stepping, same bits "
+                f"{r['graph']['same_bits_as_eager']}")
 
     peak = PEAK_VALU_TFLOPS[8]
     out = {
