@@ -656,8 +656,8 @@ def main():
     ap.add_argument("--predictor", type=int, default=None,
                     help="force the predictor mode: 0 staged kernels, k >= 1 fused tile kernel "
                          "with the k-th tile shape (for 3D: 1 = 8x8x4, 2 = 34x4x2)")
-    ap.add_argument("--split", type=int, default=None, choices=(0, 1, 2),
-                    help="force the solver form: one-phase (0), two-phase (1), edge pass (2)")
+    ap.add_argument("--split", type=int, default=None, choices=(0, 1, 2, 3),
+                    help="force the solver form: one-phase (0), two-phase (1), edge pass (2), edge-line pass (3)")
     ap.add_argument("--fp32-only", action="store_true",
                     help="skip the FP64 run (profiling of the FP32 kernels)")
     ap.add_argument("--batched-steps", type=int, default=10)

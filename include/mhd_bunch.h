@@ -247,8 +247,10 @@ mhd_status mhd_bunch_predictor_shape(const mhd_bunch* h, int32_t mode, int32_t t
  * then the whole update; 1 = two phases (face fluxes, hydro update; then edge EMFs, field
  * update) that share the shared memory, for more work-groups per compute unit; 2 = a
  * separate pass computes every edge EMF once into the workspace scratch and the tile does
- * the face fluxes and the update (no halo edges recomputed).  Same values in every form.
- * Default 0. */
+ * the face fluxes and the update (no halo edges recomputed); 3 = form 2 with that pass taken
+ * as lines of edges (one thread steps along a line and loads each corner plane once instead
+ * of twice); form 3 is form 2 itself unless all three directions are active.  Same values
+ * in every form.  Default 0; MHD_EINVAL for a form outside [0, 3]. */
 mhd_status mhd_bunch_set_solver_split(mhd_bunch* h, int32_t split);
 int32_t mhd_bunch_solver_split(const mhd_bunch* h);
 

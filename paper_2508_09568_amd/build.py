@@ -22,6 +22,10 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off: ordinary scalar FP32 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only inside one source expression, never across statements:
+    # the same expression then rounds the same wherever it is inlined, so every launch form
+    # (tile shapes, solver forms, edge and face lines) gives the same bits by construction
+    "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
 ]
 

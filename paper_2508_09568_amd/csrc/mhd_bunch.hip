@@ -229,6 +229,24 @@ void k_edges(
   }
 }
 
+// the same half-step edge EMFs as edge lines (solver form 3, patches with all three
+// directions active): BLK consecutive lines of one patch per work-group, each line marched by
+// one thread; registers alone set the occupancy, three waves per SIMD (<= 168 VGPRs)
+template <typename T, int EMF>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(3))) void k_edge_lines(
+    const PatchDev* __restrict__ pt, const BoxBlock* __restrict__ blk, T* __restrict__ S,
+    const double* __restrict__ dt, Consts<T> c, int g, int nb0, int remap,
+    const int* __restrict__ dcount) {
+  const int nb = table_count(nb0, dcount);
+  for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
+    const BoxBlock b = blk[logical_block(vb, nb, remap)];
+    if (dt[b.patch] == 0.0) continue;  // patch at rest: no EMFs needed
+    const PatchDev& P = pt[b.patch];
+    const int item = b.first + (int)threadIdx.x;
+    if (item < edge_line_count(P)) edge_line_item<EMF>(P, g, item, S, c);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_cfl(const PatchDev* __restrict__ pt,
                                              const BoxBlock* __restrict__ blk,
@@ -730,7 +748,8 @@ struct mhd_bunch {
   // predictor (mhd_bunch_set_predictor): 0 staged kernels, k >= 1 fused with tile shape
   // pshapes[k - 1]; one tile table over the predictor boxes per fused shape
   int fused = 0;
-  int split = 0;  // solver form (mhd_bunch_set_solver_split): 0 one-phase, 1 two-phase, 2 edge pass
+  int split = 0;  // solver form (mhd_bunch_set_solver_split): 0 one-phase, 1 two-phase, 2 edge
+                  // pass, 3 edge pass as edge lines
   int npshape = 0;
   TileCand pshapes[MAXPSHAPE];
   std::vector<TileDev> ptiles[MAXPSHAPE];
@@ -851,7 +870,9 @@ namespace {
 void add_blocks(std::vector<BoxBlock>& out, const PatchDev& P, int p, int kind, int g) {
   int lo[3], sz[3];
   box_of(P, kind, g, lo, sz);
-  const int n = kind == BOX_GUARD ? guard_count(P) : sz[0] * sz[1] * sz[2];
+  const int n = kind == BOX_GUARD ? guard_count(P)
+                : kind == BOX_LINE ? (P.act == 7 ? edge_line_count(P) : 0)
+                                   : sz[0] * sz[1] * sz[2];
   for (int f = 0; f < n; f += BLK) out.push_back(BoxBlock{p, f});
 }
 
@@ -919,7 +940,7 @@ void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uou
 #define MHD_TRY_EMF(X, Y, Z, EMF)                                                             \
   if (edges)                                                                                  \
     edges_launch<T, X, Y, Z, EMF>(h, nt, tl, S, dt, dx, c, s, dc);                            \
-  else if (h->split == 2)                                                                     \
+  else if (h->split >= 2)                                                                     \
     solve_launch<T, X, Y, Z, 2, EMF>(h, nt, tl, Uin, Uout, S, dt, dx, c, s, dc);              \
   else if (h->split == 1)                                                                     \
     solve_launch<T, X, Y, Z, 1, EMF>(h, nt, tl, Uin, Uout, S, dt, dx, c, s, dc);              \
@@ -945,6 +966,37 @@ void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uou
   }
 #undef MHD_TRY
 #undef MHD_TRY_EMF
+}
+
+template <typename T, int EMF>
+void edge_lines_launch(mhd_bunch* h, int nb, const BoxBlock* tb, T* S, const double* dt,
+                       const Consts<T>& c, hipStream_t s, const int* dcount) {
+  int grid = nb;
+  if (h->mode == 2 || dcount) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, reinterpret_cast<const void*>(k_edge_lines<T, EMF>), BLK, 0) != hipSuccess ||
+        occ < 1)
+      occ = 1;
+    grid = h->persistent_grid(nb, occ);
+  }
+  hipLaunchKernelGGL((k_edge_lines<T, EMF>), dim3(grid), dim3(BLK), 0, s, h->d_pt(), tb, S, dt, c,
+                     h->g, nb, h->mode >= 1 || dcount, dcount);
+}
+
+// the edge pass of solver form 3: the chunk's edge lines (or their compacted copy)
+template <typename T>
+void launch_edge_lines(mhd_bunch* h, const mhd_bunch::Chunk& ch, T* S, const double* dt,
+                       const Consts<T>& c, hipStream_t s) {
+  const int nb = ch.nblk[BOX_LINE];
+  if (!nb) return;
+  const bool cmp = h->compact && h->cslot[BOX_LINE] >= 0;
+  const BoxBlock* tb = cmp ? (const BoxBlock*)h->ctab(BOX_LINE) : h->d_blk(BOX_LINE) + ch.blk0[BOX_LINE];
+  const int* dc = cmp ? h->ccount(BOX_LINE) : nullptr;
+  if (h->emf == 1)
+    edge_lines_launch<T, 1>(h, nb, tb, S, dt, c, s, dc);
+  else
+    edge_lines_launch<T, 0>(h, nb, tb, S, dt, c, s, dc);
 }
 
 // S: scratch of one chunk of patches
@@ -1021,9 +1073,12 @@ mhd_status launch_update(mhd_bunch* h, const T* Uin, T* Uout, const double* dt, 
                          dt, c, h->g, nb, rm || dc, dc);
       h->toc(s, MHD_KERNEL_PREDICT, t0);
     }
-    if (h->split == 2 && ch.ntile[h->shape]) {
+    if (h->split >= 2 && ch.ntile[h->shape]) {
       t0 = h->tic(s);
-      launch_solve<T>(h, ch, Uin, Uout, S, dt, dx, c, s, true);
+      if (h->split == 3 && h->act == 7)
+        launch_edge_lines<T>(h, ch, S, dt, c, s);
+      else
+        launch_solve<T>(h, ch, Uin, Uout, S, dt, dx, c, s, true);
       h->toc(s, MHD_KERNEL_EDGE, t0);
     }
     if (ch.ntile[h->shape]) {
@@ -1180,6 +1235,7 @@ mhd_status launch_lts_step(mhd_bunch* h, T* Ucur, T* Unew, T* Uprev, double* t, 
     add(BOX_ALL, 1);
     if (!dt_fixed) add(BOX_INTERIOR, 1);
     add(NBOX + h->shape, 2);
+    if (h->split == 3 && h->act == 7) add(BOX_LINE, 1);
     if (h->fused) {
       add(NBOX + MAXSHAPE + h->fused - 1, 2);
     } else {
@@ -1400,7 +1456,7 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
       h->chunks[c].p1 = c + 1 < h->chunks.size() ? h->chunks[c + 1].p0 : h->P;
   }
   for (auto& ch : h->chunks) {
-    for (int kind : {BOX_PRIM, BOX_EN, BOX_PRED}) {
+    for (int kind : {BOX_PRIM, BOX_EN, BOX_PRED, BOX_LINE}) {
       ch.blk0[kind] = (int)h->blocks[kind].size();
       for (int p = ch.p0; p < ch.p1; ++p) add_blocks(h->blocks[kind], h->pt[p], p, kind, g);
       ch.nblk[kind] = (int)h->blocks[kind].size() - ch.blk0[kind];
@@ -1802,7 +1858,7 @@ mhd_status mhd_bunch_predictor_shape(const mhd_bunch* h, int32_t mode, int32_t* 
 }
 
 mhd_status mhd_bunch_set_solver_split(mhd_bunch* h, int32_t split) {
-  if (!h || split < 0 || split > 2) return MHD_EINVAL;
+  if (!h || split < 0 || split > 3) return MHD_EINVAL;
   h->split = split;
   return MHD_OK;
 }
@@ -1839,7 +1895,7 @@ mhd_status mhd_bunch_autotune(mhd_bunch* h, const void* Uin, void* Uout, const d
     h->shape = k / NMODE;
     h->mode = k % NMODE;
     float kbest = 0.0f;
-    for (int sp = 0; sp < 3 && ok; ++sp) {
+    for (int sp = 0; sp < (h->act == 7 ? 4 : 3) && ok; ++sp) {
       h->split = sp;
       float t = 0.0f;
       time_it(&t);

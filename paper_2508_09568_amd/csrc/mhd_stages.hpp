@@ -51,7 +51,7 @@ struct TileDev {    // one work-group of the solver: tile origin inside the inte
 };
 
 enum BoxKind { BOX_PRIM = 0, BOX_EN = 1, BOX_PRED = 2, BOX_INTERIOR = 3, BOX_ALL = 4, BOX_GUARD = 5,
-               NBOX = 6 };
+               BOX_LINE = 6, NBOX = 7 };
 
 __host__ __device__ __forceinline__ bool active(const PatchDev& P, int d) { return (P.act >> d) & 1; }
 
@@ -533,6 +533,238 @@ __host__ __device__ __forceinline__ S edge_px_point(const PatchDev& P, int g, in
     return uct_hlld_emf(Call, c);
   else
     return u.finish(c);
+}
+
+// value of lane 0 of the wavefront (the caller guarantees it is the same on every lane)
+__host__ __device__ __forceinline__ int wave_uniform(int v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_readfirstlane(v);
+#else
+  return v;
+#endif
+}
+
+// ------------------------------------------------------------------ edge lines
+// The edges a patch owns, taken as lines of consecutive edges, one line per thread: edges
+// along x and along y stepped in z, edges along z stepped in y.  Two of an edge's four corner
+// cells lie in the line's current plane (row) and two in the previous one, so each step loads
+// the values of one new plane and keeps the previous plane's in registers: about half the
+// loads per edge of edge_point / edge_px_point, with the same arithmetic on the same values
+// (corner_from, then the same UCT combination), so the EMFs are bitwise theirs.  For patches
+// with all three directions active.
+// Per patch the lines are numbered in three segments, each padded to whole wavefronts:
+//   x edges: (lx, ly) in [0, n_x) x [0, n_y], lz = 0 .. n_z
+//   y edges: (lx, ly) in [0, n_x] x [0, n_y), lz = 0 .. n_z
+//   z edges: (lx, lz) in [0, n_x] x [0, n_z), ly = 0 .. n_y
+// i.e. the lower edges of the patch's cells plus the upper layers: each edge of the patch once.
+__host__ __device__ __forceinline__ int pad_wave(int n) { return (n + 63) / 64 * 64; }
+__host__ __device__ __forceinline__ void edge_line_segments(const PatchDev& P, int L[3]) {
+  const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+  L[0] = pad_wave(nx * (ny + 1));
+  L[1] = pad_wave((nx + 1) * ny);
+  L[2] = pad_wave((nx + 1) * nz);
+}
+__host__ __device__ __forceinline__ int edge_line_count(const PatchDev& P) {
+  int L[3];
+  edge_line_segments(P, L);
+  return L[0] + L[1] + L[2];
+}
+
+// the 5 corner components of predictor cell wc and their slopes along a and b (edge along E)
+template <int E, typename S, class AW>
+__host__ __device__ __forceinline__ void corner_vals(const AW& w, uint32_t wc, uint32_t Nw, S v[5],
+                                                     S sla[5], S slb[5]) {
+  constexpr int a = (E + 1) % 3, b = (E + 2) % 3;
+  constexpr int comp[5] = {0, 1 + a, 1 + b, 4, 5 + E};
+  #pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    const int m = comp[t];
+    v[t] = w(wc + m * Nw);
+    sla[t] = w(wc + slope_slot(a, m) * Nw);
+    slb[t] = w(wc + slope_slot(b, m) * Nw);
+  }
+}
+
+// one corner into the EMF: UCT-HLL accumulates it, UCT-HLLD keeps it for the end
+template <int EMF, typename S>
+struct EdgeAcc {
+  UctAcc<S> u;
+  S C[EMF == 1 ? 4 : 1][7];
+  __host__ __device__ __forceinline__ void corner(int k, const S v[5], const S sla[5], const S slb[5],
+                                                  S BA, S tA, S BB, S tB, int sa, int sb,
+                                                  const Consts<S>& c) {
+    if constexpr (EMF == 1) {
+      corner_from(v, sla, slb, BA, tA, BB, tB, sa, sb, c, C[k]);
+    } else {
+      S Ck[7];
+      corner_from(v, sla, slb, BA, tA, BB, tB, sa, sb, c, Ck);
+      u.add(k, Ck, c);
+    }
+  }
+  __host__ __device__ __forceinline__ S finish(const Consts<S>& c) const {
+    if constexpr (EMF == 1)
+      return uct_hlld_emf(C, c);
+    else
+      return u.finish(c);
+  }
+};
+
+template <typename S>
+__host__ __device__ __forceinline__ void keep5(S d[5], const S s[5]) {
+  #pragma unroll
+  for (int t = 0; t < 5; ++t) d[t] = s[t];
+}
+
+// Edges along x at (i, j, k0 .. k0 + nk - 1) (padded indices), written to out[s * ostride].
+// a = y, b = z.  Corner cells of the edge at plane k: A = (j - 1, k), B = (j, k) and A', B'
+// one plane below; SW = A', SE = B', NW = A, NE = B.  The faces the corners read: B_y on the
+// lower y face of B' (SW, SE) or B (NW, NE), B_z on the lower z face of A (SW, NW) or B (SE, NE).
+template <int EMF, typename S, class AW>
+__host__ __device__ __forceinline__ void edge_line_x(const PatchDev& P, int g, int i, int j, int k0,
+                                                     int nk, const AW& w, S* out, int64_t ostride,
+                                                     const Consts<S>& c) {
+  const uint32_t Nw = (uint32_t)P.Nwc;
+  const uint32_t oa = (uint32_t)P.woff[1], ob = (uint32_t)P.woff[2];
+  uint32_t wb = (uint32_t)wcell_of(P, g, i, j, k0) - ob;  // B of the plane below the first edge
+  S pv[2][5], psa[2][5], psb[2][5];
+  corner_vals<0>(w, wb - oa, Nw, pv[0], psa[0], psb[0]);
+  corner_vals<0>(w, wb, Nw, pv[1], psa[1], psb[1]);
+  S pBA = w(wb + (W_BH + 1) * Nw), ptA = w(wb + dbf_slot(1, 2) * Nw);
+  for (int s = 0; s < nk; ++s) {
+    wb += ob;
+    S v[2][5], sla[2][5], slb[2][5];
+    corner_vals<0>(w, wb - oa, Nw, v[0], sla[0], slb[0]);
+    corner_vals<0>(w, wb, Nw, v[1], sla[1], slb[1]);
+    const S BA = w(wb + (W_BH + 1) * Nw), tA = w(wb + dbf_slot(1, 2) * Nw);
+    const S BBa = w(wb - oa + (W_BH + 2) * Nw), tBa = w(wb - oa + dbf_slot(2, 1) * Nw);
+    const S BBb = w(wb + (W_BH + 2) * Nw), tBb = w(wb + dbf_slot(2, 1) * Nw);
+    EdgeAcc<EMF, S> acc;
+    acc.corner(0, pv[0], psa[0], psb[0], pBA, ptA, BBa, tBa, +1, +1, c);  // SW
+    acc.corner(1, pv[1], psa[1], psb[1], pBA, ptA, BBb, tBb, -1, +1, c);  // SE
+    acc.corner(2, v[0], sla[0], slb[0], BA, tA, BBa, tBa, +1, -1, c);     // NW
+    acc.corner(3, v[1], sla[1], slb[1], BA, tA, BBb, tBb, -1, -1, c);     // NE
+    out[s * ostride] = acc.finish(c);
+    #pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      keep5(pv[h], v[h]);
+      keep5(psa[h], sla[h]);
+      keep5(psb[h], slb[h]);
+    }
+    pBA = BA;
+    ptA = tA;
+    MHD_SCHED_FENCE();
+  }
+}
+
+// Edges along y at (i, j, k0 .. k0 + nk - 1): a = z, b = x.  A row is the x-neighbour pair
+// (i - 1, i) of one plane (values loaded in pairs); the row below has sa = +1 (corners SW at
+// i - 1, NW at i), the current row sa = -1 (SE, NE).  B_z on the lower z faces of the current
+// row's pair (both rows), B_x on the lower x face of cell i of each row.
+template <int EMF, typename S, class AW>
+__host__ __device__ __forceinline__ void edge_line_y(const PatchDev& P, int g, int i, int j, int k0,
+                                                     int nk, const AW& w, S* out, int64_t ostride,
+                                                     const Consts<S>& c) {
+  const uint32_t Nw = (uint32_t)P.Nwc;
+  const uint32_t oz = (uint32_t)P.woff[2];
+  uint32_t c0 = (uint32_t)wcell_of(P, g, i, j, k0) - 1u - oz;
+  S pv[2][5], psa[2][5], psb[2][5];
+  corner_vals_pair<1>(w, c0, Nw, pv, psa, psb);
+  S pBB = w(c0 + 1u + W_BH * Nw), ptB = w(c0 + 1u + dbf_slot(0, 2) * Nw);
+  for (int s = 0; s < nk; ++s) {
+    c0 += oz;
+    S v[2][5], sla[2][5], slb[2][5];
+    corner_vals_pair<1>(w, c0, Nw, v, sla, slb);
+    S BA[2], tA[2];
+    w.pair(c0 + (W_BH + 2) * Nw, BA[0], BA[1]);
+    w.pair(c0 + dbf_slot(2, 0) * Nw, tA[0], tA[1]);
+    const S BB = w(c0 + 1u + W_BH * Nw), tB = w(c0 + 1u + dbf_slot(0, 2) * Nw);
+    EdgeAcc<EMF, S> acc;
+    acc.corner(0, pv[0], psa[0], psb[0], BA[0], tA[0], pBB, ptB, +1, +1, c);
+    acc.corner(2, pv[1], psa[1], psb[1], BA[1], tA[1], pBB, ptB, +1, -1, c);
+    acc.corner(1, v[0], sla[0], slb[0], BA[0], tA[0], BB, tB, -1, +1, c);
+    acc.corner(3, v[1], sla[1], slb[1], BA[1], tA[1], BB, tB, -1, -1, c);
+    out[s * ostride] = acc.finish(c);
+    #pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      keep5(pv[h], v[h]);
+      keep5(psa[h], sla[h]);
+      keep5(psb[h], slb[h]);
+    }
+    pBB = BB;
+    ptB = tB;
+    MHD_SCHED_FENCE();
+  }
+}
+
+// Edges along z at (i, j0 .. j0 + nj - 1, k): a = x, b = y.  A row is the x-neighbour pair
+// (i - 1, i) of one y row; the row below has sb = +1 (SW at i - 1, SE at i), the current row
+// sb = -1 (NW, NE).  B_x on the lower x face of cell i of each row, B_y on the lower y faces of
+// the current row's pair (both rows).
+template <int EMF, typename S, class AW>
+__host__ __device__ __forceinline__ void edge_line_z(const PatchDev& P, int g, int i, int j0, int k,
+                                                     int nj, const AW& w, S* out, int64_t ostride,
+                                                     const Consts<S>& c) {
+  const uint32_t Nw = (uint32_t)P.Nwc;
+  const uint32_t oy = (uint32_t)P.woff[1];
+  uint32_t c0 = (uint32_t)wcell_of(P, g, i, j0, k) - 1u - oy;
+  S pv[2][5], psa[2][5], psb[2][5];
+  corner_vals_pair<2>(w, c0, Nw, pv, psa, psb);
+  S pBA = w(c0 + 1u + W_BH * Nw), ptA = w(c0 + 1u + dbf_slot(0, 1) * Nw);
+  for (int s = 0; s < nj; ++s) {
+    c0 += oy;
+    S v[2][5], sla[2][5], slb[2][5];
+    corner_vals_pair<2>(w, c0, Nw, v, sla, slb);
+    S BB[2], tB[2];
+    w.pair(c0 + (W_BH + 1) * Nw, BB[0], BB[1]);
+    w.pair(c0 + dbf_slot(1, 0) * Nw, tB[0], tB[1]);
+    const S BA = w(c0 + 1u + W_BH * Nw), tA = w(c0 + 1u + dbf_slot(0, 1) * Nw);
+    EdgeAcc<EMF, S> acc;
+    acc.corner(0, pv[0], psa[0], psb[0], pBA, ptA, BB[0], tB[0], +1, +1, c);
+    acc.corner(1, pv[1], psa[1], psb[1], pBA, ptA, BB[1], tB[1], -1, +1, c);
+    acc.corner(2, v[0], sla[0], slb[0], BA, tA, BB[0], tB[0], +1, -1, c);
+    acc.corner(3, v[1], sla[1], slb[1], BA, tA, BB[1], tB[1], -1, -1, c);
+    out[s * ostride] = acc.finish(c);
+    #pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      keep5(pv[h], v[h]);
+      keep5(psa[h], sla[h]);
+      keep5(psb[h], slb[h]);
+    }
+    pBA = BA;
+    ptA = tA;
+    MHD_SCHED_FENCE();
+  }
+}
+
+// Line `item` of a patch's edge lines (numbering above): its half-step EMFs into the scratch
+// slots of the time-n EMFs, E_e of padded cell (i, j, k) at S[P.sbase + (8 + e) Nc + cell].
+template <int EMF, typename T>
+__host__ __device__ __forceinline__ void edge_line_item(const PatchDev& P, int g, int item, T* S,
+                                                        const Consts<T>& c) {
+  int L[3];
+  edge_line_segments(P, L);
+  const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+  const LdRel<T> w{S + P.wbase};
+  T* eb = S + P.sbase + 8 * P.Nc;
+  const int seg = wave_uniform(item < L[0] ? 0 : item < L[0] + L[1] ? 1 : 2);
+  if (seg == 0) {
+    const int lx = item % nx, ly = item / nx;
+    if (ly > ny) return;
+    edge_line_x<EMF>(P, g, g + lx, g + ly, g, nz + 1, w, eb + cell_of(P, g + lx, g + ly, g),
+                     P.off[2], c);
+  } else if (seg == 1) {
+    const int r = item - L[0];
+    const int lx = r % (nx + 1), ly = r / (nx + 1);
+    if (ly >= ny) return;
+    edge_line_y<EMF>(P, g, g + lx, g + ly, g, nz + 1, w,
+                     eb + P.Nc + cell_of(P, g + lx, g + ly, g), P.off[2], c);
+  } else {
+    const int r = item - L[0] - L[1];
+    const int lx = r % (nx + 1), lz = r / (nx + 1);
+    if (lz >= nz) return;
+    edge_line_z<EMF>(P, g, g + lx, g, g + lz, ny + 1, w,
+                     eb + 2 * P.Nc + cell_of(P, g + lx, g, g + lz), P.off[1], c);
+  }
 }
 
 // ------------------------------------------------ forward writers of stages 1-3
@@ -1036,14 +1268,6 @@ __host__ __device__ __forceinline__ int predict_tile(X& ex, T* L, const PatchDev
 // One tile of TX x TY x TZ interior cells: HLLD fluxes on its faces, edge EMFs on its
 // edges (shared memory), then the conservative + constrained-transport update of its
 // cells.  X provides tid(), nthr() and sync() of the work-group.
-// value of lane 0 of the wavefront (the caller guarantees it is the same on every lane)
-__host__ __device__ __forceinline__ int wave_uniform(int v) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  return __builtin_amdgcn_readfirstlane(v);
-#else
-  return v;
-#endif
-}
 
 template <int TX, int TY, int TZ>
 struct TileShape {

@@ -133,6 +133,13 @@ def test_predictor_modes_are_listed_and_range_checked(B, dims, shapes):
             assert B.mhd_bunch_set_predictor(h, bad) == B.MHD_EINVAL
         assert B.mhd_bunch_set_predictor(h, n - 1) == B.MHD_OK
         assert B.mhd_bunch_predictor(h) == n - 1
+        # solver forms 0..3 (form 3 is form 2 unless all three directions are active)
+        assert B.mhd_bunch_solver_split(h) == 0
+        for bad in (-1, 4):
+            assert B.mhd_bunch_set_solver_split(h, bad) == B.MHD_EINVAL
+        for form in (3, 0):
+            assert B.mhd_bunch_set_solver_split(h, form) == B.MHD_OK
+            assert B.mhd_bunch_solver_split(h) == form
     finally:
         B.mhd_bunch_destroy(h)
 

@@ -57,7 +57,7 @@ def test_every_launch_configuration_gives_identical_bits(case, precision):
     for fused in range(len(modes)):
         B.set_predictor(fused)
         assert B.predictor() == fused
-        for split in (0, 1, 2):
+        for split in range(4):
             B.set_solver_split(split)
             assert B.solver_split() == split
             for i, cfg in enumerate(cfgs):

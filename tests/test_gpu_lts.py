@@ -277,15 +277,16 @@ def test_bad_given_step_stops_the_patch_and_is_reported():
         assert np.array_equal(L.interior(got, p), L.interior(U, p))
 
 
-@pytest.mark.parametrize("case", ["periodic", "outflow_corner"])
-def test_compacted_captured_and_chunked_runs_agree_bitwise(case):
+@pytest.mark.parametrize("case,form", [("periodic", 0), ("outflow_corner", 0), ("periodic", 3)])
+def test_compacted_captured_and_chunked_runs_agree_bitwise(case, form):
     """The same local-time-stepping run (each patch at its own CFL step) three ways: one
     chunk, so every step compacts its launch tables to the ready patches (eager calls); the
     same with the steps captured in HIP graphs; and a bunch processed in several scratch
-    chunks, whose steps launch over every patch.  All give the same bits and times."""
+    chunks, whose steps launch over every patch.  All give the same bits and times (solver
+    form 0, and form 3, whose edge-line table is compacted as well)."""
     import torch
     from paper_2508_09568_amd import lts
-    log(f"[gpu] lts compacted / captured / chunked, case {case}")
+    log(f"[gpu] lts compacted / captured / chunked, case {case}, solver form {form}")
     w, U = _turb3d(case)
     L = w.layout
     import oracle
@@ -294,6 +295,7 @@ def test_compacted_captured_and_chunked_runs_agree_bitwise(case):
     t_end = 6 * float(own.min())
     Ud, dxd, nbd = dev(U), dev(w.dx), dev(w.nbr.astype(np.int32))
     B1 = make_bunch(L, w.gamma)
+    B1.set_solver_split(form)
     Ua, ta, na, ca = lts.run(B1, Ud, dxd, nbd, t_end, check_every=1)
     assert B1.check() == 0
     Ug, tg, ng = lts.run_graph(B1, Ud, dxd, nbd, t_end, steps_per_graph=4)

@@ -103,7 +103,7 @@ def test_every_launch_configuration_gives_identical_bits(case, precision):
     n = 0
     for fused in range(len(B.predictor_modes())):
         B.set_predictor(fused)
-        for split in (0, 1, 2):
+        for split in range(4):
             B.set_solver_split(split)
             for i in range(len(B.tile_configs())):
                 B.set_tile(i)
