@@ -141,9 +141,30 @@ struct Ld {
 template <typename T>
 struct LdRel {
   const T* p;
+  uint32_t Nw;  // elements per slot of the block (slot v of cell c at v Nw + c)
   __host__ __device__ __forceinline__ T operator()(uint32_t i) const {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) +
                                        (uint32_t)(i * (uint32_t)sizeof(T)));
+  }
+  // slot v of cell c: the slot's base is uniform across the wavefront (scalar registers) and
+  // the cell's byte offset is shared by every slot read at that cell, so a load spends no
+  // vector instruction on its address beyond the offset of its cell
+  __host__ __device__ __forceinline__ const char* slot(int v) const {
+    return reinterpret_cast<const char*>(p) + (size_t)((uint32_t)v * Nw) * sizeof(T);
+  }
+  __host__ __device__ __forceinline__ T at(uint32_t c, int v) const {
+    return *reinterpret_cast<const T*>(slot(v) + (uint32_t)(c * (uint32_t)sizeof(T)));
+  }
+  __host__ __device__ __forceinline__ void pair_at(uint32_t c, int v, T& a, T& b) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef T v2 __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+    const v2 x = *reinterpret_cast<const v2*>(slot(v) + (uint32_t)(c * (uint32_t)sizeof(T)));
+    a = x.x;
+    b = x.y;
+#else
+    a = at(c, v);
+    b = at(c + 1u, v);
+#endif
   }
   // elements i and i + 1 (x neighbours in a predictor block) by one memory instruction: the
   // vector units fetch 16 bytes per lane at the cost of 8 (the address only needs the
@@ -166,8 +187,14 @@ template <typename T>
 struct LdSeed {
   const T* p;
   int64_t seed;  // element whose derivative is taken (-1: none)
+  int64_t Nw;    // elements per slot where the block holds predictor values
   __host__ __device__ __forceinline__ Dual<T> operator()(int64_t i) const {
     return Dual<T>(p[i], i == seed ? T(1) : T(0));
+  }
+  __host__ __device__ __forceinline__ Dual<T> at(int64_t c, int v) const { return (*this)(v * Nw + c); }
+  __host__ __device__ __forceinline__ void pair_at(int64_t c, int v, Dual<T>& a, Dual<T>& b) const {
+    a = at(c, v);
+    b = at(c + 1, v);
   }
 };
 
@@ -322,7 +349,6 @@ template <typename S, class AW>
 __host__ __device__ __forceinline__ void face_point(const PatchDev& P, int g, int d, int i, int j,
                                                     int k, const AW& w, const Consts<S>& c,
                                                     S F[5]) {
-  const uint32_t Nw = (uint32_t)P.Nwc;
   const uint32_t wr = (uint32_t)wcell_of(P, g, i, j, k);
   const uint32_t wl = wr - (uint32_t)P.woff[d];
   const int a = (d + 1) % 3, b = (d + 2) % 3;
@@ -331,14 +357,14 @@ __host__ __device__ __forceinline__ void face_point(const PatchDev& P, int g, in
   for (int t = 0; t < 7; ++t) {
     const int m = comp[t];
     const int sl = slope_slot(d, m);
-    s[0][t] = w(wl + m * Nw) + S(0.5) * w(wl + sl * Nw);
-    s[1][t] = w(wr + m * Nw) - S(0.5) * w(wr + sl * Nw);
+    s[0][t] = w.at(wl, m) + S(0.5) * w.at(wl, sl);
+    s[1][t] = w.at(wr, m) - S(0.5) * w.at(wr, sl);
   }
   for (int k2 = 0; k2 < 2; ++k2) {
     if (s[k2][0] < c.rho_floor) s[k2][0] = c.rho_floor;
     if (s[k2][4] < c.p_floor) s[k2][4] = c.p_floor;
   }
-  const S bn = w(wr + (W_BH + d) * Nw);
+  const S bn = w.at(wr, W_BH + d);
   hlld_flux(s, bn, c, F);
 }
 
@@ -369,20 +395,19 @@ template <typename S, class AW>
 __host__ __device__ __forceinline__ void corner_state(const PatchDev& P, const AW& w, uint32_t wc,
                                                       int e, int sa, int sb, const Consts<S>& c,
                                                       S C[7]) {
-  const uint32_t Nw = (uint32_t)P.Nwc;
   const int a = (e + 1) % 3, b = (e + 2) % 3;
   const int comp[5] = {0, 1 + a, 1 + b, 4, 5 + e};
   S v[5], sla[5], slb[5];
   for (int t = 0; t < 5; ++t) {
     const int m = comp[t];
-    v[t] = w(wc + m * Nw);
-    sla[t] = w(wc + slope_slot(a, m) * Nw);
-    slb[t] = w(wc + slope_slot(b, m) * Nw);
+    v[t] = w.at(wc, m);
+    sla[t] = w.at(wc, slope_slot(a, m));
+    slb[t] = w.at(wc, slope_slot(b, m));
   }
   const uint32_t fa = wc + (sa > 0 ? (uint32_t)P.woff[a] : 0u);
   const uint32_t fb = wc + (sb > 0 ? (uint32_t)P.woff[b] : 0u);
-  corner_from(v, sla, slb, w(fa + (W_BH + a) * Nw), w(fa + dbf_slot(a, b) * Nw),
-              w(fb + (W_BH + b) * Nw), w(fb + dbf_slot(b, a) * Nw), sa, sb, c, C);
+  corner_from(v, sla, slb, w.at(fa, W_BH + a), w.at(fa, dbf_slot(a, b)),
+              w.at(fb, W_BH + b), w.at(fb, dbf_slot(b, a)), sa, sb, c, C);
 }
 
 // -------------------------------------------------------- stage 4b: edge EMF
@@ -425,23 +450,22 @@ __host__ __device__ __forceinline__ S edge_point(const PatchDev& P, int g, int e
 // Slot values of the 5 corner components and their slopes along a and b of cell wc and of
 // wc + 1 (for one edge direction E).
 template <int E, typename S, class AW>
-__host__ __device__ __forceinline__ void corner_vals_pair(const AW& w, uint32_t wc, uint32_t Nw,
-                                                          S v[2][5], S sla[2][5], S slb[2][5]) {
+__host__ __device__ __forceinline__ void corner_vals_pair(const AW& w, uint32_t wc, S v[2][5],
+                                                          S sla[2][5], S slb[2][5]) {
   constexpr int a = (E + 1) % 3, b = (E + 2) % 3;
   constexpr int comp[5] = {0, 1 + a, 1 + b, 4, 5 + E};
   #pragma unroll
   for (int t = 0; t < 5; ++t) {
     const int m = comp[t];
-    w.pair(wc + m * Nw, v[0][t], v[1][t]);
-    w.pair(wc + slope_slot(a, m) * Nw, sla[0][t], sla[1][t]);
-    w.pair(wc + slope_slot(b, m) * Nw, slb[0][t], slb[1][t]);
+    w.pair_at(wc, m, v[0][t], v[1][t]);
+    w.pair_at(wc, slope_slot(a, m), sla[0][t], sla[1][t]);
+    w.pair_at(wc, slope_slot(b, m), slb[0][t], slb[1][t]);
   }
 }
 
 template <typename S, class AW>
 __host__ __device__ __forceinline__ void face_x_point(const PatchDev& P, int g, int i, int j, int k,
                                                       const AW& w, const Consts<S>& c, S F[5]) {
-  const uint32_t Nw = (uint32_t)P.Nwc;
   const uint32_t wl = (uint32_t)wcell_of(P, g, i, j, k) - 1u;
   constexpr int comp[7] = {0, 1, 2, 3, 4, 6, 7};
   S s[2][7];
@@ -449,8 +473,8 @@ __host__ __device__ __forceinline__ void face_x_point(const PatchDev& P, int g, 
   for (int t = 0; t < 7; ++t) {
     const int m = comp[t];
     S vl, vr, ql, qr;
-    w.pair(wl + m * Nw, vl, vr);
-    w.pair(wl + slope_slot(0, m) * Nw, ql, qr);
+    w.pair_at(wl, m, vl, vr);
+    w.pair_at(wl, slope_slot(0, m), ql, qr);
     s[0][t] = vl + S(0.5) * ql;
     s[1][t] = vr - S(0.5) * qr;
   }
@@ -459,7 +483,7 @@ __host__ __device__ __forceinline__ void face_x_point(const PatchDev& P, int g, 
     if (s[k2][0] < c.rho_floor) s[k2][0] = c.rho_floor;
     if (s[k2][4] < c.p_floor) s[k2][4] = c.p_floor;
   }
-  hlld_flux(s, w(wl + 1u + W_BH * Nw), c, F);
+  hlld_flux(s, w.at(wl + 1u, W_BH), c, F);
 }
 
 template <int E, int EMF, typename S, class AW>
@@ -467,7 +491,6 @@ __host__ __device__ __forceinline__ S edge_px_point(const PatchDev& P, int g, in
                                                     const AW& w, const Consts<S>& c) {
   static_assert(E == 1 || E == 2, "edges along y or z");
   constexpr int a = (E + 1) % 3, b = (E + 2) % 3;
-  const uint32_t Nw = (uint32_t)P.Nwc;
   const uint32_t wc = (uint32_t)wcell_of(P, g, i, j, k);
   // the transverse direction that is not x: corners one cell apart along it
   constexpr int t = E == 2 ? b : a;  // E = z: (a, b) = (x, y); E = y: (a, b) = (z, x)
@@ -479,7 +502,7 @@ __host__ __device__ __forceinline__ S edge_px_point(const PatchDev& P, int g, in
     // cells (x - 1, row) and (x, row) along t: row 0 at t - 1, row 1 at t
     const uint32_t c0 = wc - 1u - (row == 0 ? ot : 0u);
     S v[2][5], sla[2][5], slb[2][5];
-    corner_vals_pair<E>(w, c0, Nw, v, sla, slb);
+    corner_vals_pair<E>(w, c0, v, sla, slb);
     // corner signs (sa, sb) and corner index of the x - 1 and x cells of this row
     int sa[2], sb[2], kk[2];
     if (E == 2) {  // a = x, b = y: row 0 = (SW, SE), row 1 = (NW, NE)
@@ -502,15 +525,15 @@ __host__ __device__ __forceinline__ S edge_px_point(const PatchDev& P, int g, in
       if (h == 0) {
         // the face values of both corners of the row, paired where they are x neighbours
         if (E == 2) {  // a = x: both corners read B_x on the face at x (cell c0 + 1)
-          BA[0] = BA[1] = w(c0 + 1u + (W_BH + a) * Nw);
-          tA[0] = tA[1] = w(c0 + 1u + dbf_slot(a, b) * Nw);
-          w.pair(fb + (W_BH + b) * Nw, BB[0], BB[1]);
-          w.pair(fb + dbf_slot(b, a) * Nw, tB[0], tB[1]);
+          BA[0] = BA[1] = w.at(c0 + 1u, W_BH + a);
+          tA[0] = tA[1] = w.at(c0 + 1u, dbf_slot(a, b));
+          w.pair_at(fb, W_BH + b, BB[0], BB[1]);
+          w.pair_at(fb, dbf_slot(b, a), tB[0], tB[1]);
         } else {       // b = x: both corners read B_x on the face at x (cell c0 + 1)
-          w.pair(fa + (W_BH + a) * Nw, BA[0], BA[1]);
-          w.pair(fa + dbf_slot(a, b) * Nw, tA[0], tA[1]);
-          BB[0] = BB[1] = w(c0 + 1u + (W_BH + b) * Nw);
-          tB[0] = tB[1] = w(c0 + 1u + dbf_slot(b, a) * Nw);
+          w.pair_at(fa, W_BH + a, BA[0], BA[1]);
+          w.pair_at(fa, dbf_slot(a, b), tA[0], tA[1]);
+          BB[0] = BB[1] = w.at(c0 + 1u, W_BH + b);
+          tB[0] = tB[1] = w.at(c0 + 1u, dbf_slot(b, a));
         }
       }
     }
@@ -572,16 +595,16 @@ __host__ __device__ __forceinline__ int edge_line_count(const PatchDev& P) {
 
 // the 5 corner components of predictor cell wc and their slopes along a and b (edge along E)
 template <int E, typename S, class AW>
-__host__ __device__ __forceinline__ void corner_vals(const AW& w, uint32_t wc, uint32_t Nw, S v[5],
-                                                     S sla[5], S slb[5]) {
+__host__ __device__ __forceinline__ void corner_vals(const AW& w, uint32_t wc, S v[5], S sla[5],
+                                                     S slb[5]) {
   constexpr int a = (E + 1) % 3, b = (E + 2) % 3;
   constexpr int comp[5] = {0, 1 + a, 1 + b, 4, 5 + E};
   #pragma unroll
   for (int t = 0; t < 5; ++t) {
     const int m = comp[t];
-    v[t] = w(wc + m * Nw);
-    sla[t] = w(wc + slope_slot(a, m) * Nw);
-    slb[t] = w(wc + slope_slot(b, m) * Nw);
+    v[t] = w.at(wc, m);
+    sla[t] = w.at(wc, slope_slot(a, m));
+    slb[t] = w.at(wc, slope_slot(b, m));
   }
 }
 
@@ -623,21 +646,20 @@ template <int EMF, typename S, class AW>
 __host__ __device__ __forceinline__ void edge_line_x(const PatchDev& P, int g, int i, int j, int k0,
                                                      int nk, const AW& w, S* out, int64_t ostride,
                                                      const Consts<S>& c) {
-  const uint32_t Nw = (uint32_t)P.Nwc;
   const uint32_t oa = (uint32_t)P.woff[1], ob = (uint32_t)P.woff[2];
   uint32_t wb = (uint32_t)wcell_of(P, g, i, j, k0) - ob;  // B of the plane below the first edge
   S pv[2][5], psa[2][5], psb[2][5];
-  corner_vals<0>(w, wb - oa, Nw, pv[0], psa[0], psb[0]);
-  corner_vals<0>(w, wb, Nw, pv[1], psa[1], psb[1]);
-  S pBA = w(wb + (W_BH + 1) * Nw), ptA = w(wb + dbf_slot(1, 2) * Nw);
+  corner_vals<0>(w, wb - oa, pv[0], psa[0], psb[0]);
+  corner_vals<0>(w, wb, pv[1], psa[1], psb[1]);
+  S pBA = w.at(wb, W_BH + 1), ptA = w.at(wb, dbf_slot(1, 2));
   for (int s = 0; s < nk; ++s) {
     wb += ob;
     S v[2][5], sla[2][5], slb[2][5];
-    corner_vals<0>(w, wb - oa, Nw, v[0], sla[0], slb[0]);
-    corner_vals<0>(w, wb, Nw, v[1], sla[1], slb[1]);
-    const S BA = w(wb + (W_BH + 1) * Nw), tA = w(wb + dbf_slot(1, 2) * Nw);
-    const S BBa = w(wb - oa + (W_BH + 2) * Nw), tBa = w(wb - oa + dbf_slot(2, 1) * Nw);
-    const S BBb = w(wb + (W_BH + 2) * Nw), tBb = w(wb + dbf_slot(2, 1) * Nw);
+    corner_vals<0>(w, wb - oa, v[0], sla[0], slb[0]);
+    corner_vals<0>(w, wb, v[1], sla[1], slb[1]);
+    const S BA = w.at(wb, W_BH + 1), tA = w.at(wb, dbf_slot(1, 2));
+    const S BBa = w.at(wb - oa, W_BH + 2), tBa = w.at(wb - oa, dbf_slot(2, 1));
+    const S BBb = w.at(wb, W_BH + 2), tBb = w.at(wb, dbf_slot(2, 1));
     EdgeAcc<EMF, S> acc;
     acc.corner(0, pv[0], psa[0], psb[0], pBA, ptA, BBa, tBa, +1, +1, c);  // SW
     acc.corner(1, pv[1], psa[1], psb[1], pBA, ptA, BBb, tBb, -1, +1, c);  // SE
@@ -664,20 +686,19 @@ template <int EMF, typename S, class AW>
 __host__ __device__ __forceinline__ void edge_line_y(const PatchDev& P, int g, int i, int j, int k0,
                                                      int nk, const AW& w, S* out, int64_t ostride,
                                                      const Consts<S>& c) {
-  const uint32_t Nw = (uint32_t)P.Nwc;
   const uint32_t oz = (uint32_t)P.woff[2];
   uint32_t c0 = (uint32_t)wcell_of(P, g, i, j, k0) - 1u - oz;
   S pv[2][5], psa[2][5], psb[2][5];
-  corner_vals_pair<1>(w, c0, Nw, pv, psa, psb);
-  S pBB = w(c0 + 1u + W_BH * Nw), ptB = w(c0 + 1u + dbf_slot(0, 2) * Nw);
+  corner_vals_pair<1>(w, c0, pv, psa, psb);
+  S pBB = w.at(c0 + 1u, W_BH), ptB = w.at(c0 + 1u, dbf_slot(0, 2));
   for (int s = 0; s < nk; ++s) {
     c0 += oz;
     S v[2][5], sla[2][5], slb[2][5];
-    corner_vals_pair<1>(w, c0, Nw, v, sla, slb);
+    corner_vals_pair<1>(w, c0, v, sla, slb);
     S BA[2], tA[2];
-    w.pair(c0 + (W_BH + 2) * Nw, BA[0], BA[1]);
-    w.pair(c0 + dbf_slot(2, 0) * Nw, tA[0], tA[1]);
-    const S BB = w(c0 + 1u + W_BH * Nw), tB = w(c0 + 1u + dbf_slot(0, 2) * Nw);
+    w.pair_at(c0, W_BH + 2, BA[0], BA[1]);
+    w.pair_at(c0, dbf_slot(2, 0), tA[0], tA[1]);
+    const S BB = w.at(c0 + 1u, W_BH), tB = w.at(c0 + 1u, dbf_slot(0, 2));
     EdgeAcc<EMF, S> acc;
     acc.corner(0, pv[0], psa[0], psb[0], BA[0], tA[0], pBB, ptB, +1, +1, c);
     acc.corner(2, pv[1], psa[1], psb[1], BA[1], tA[1], pBB, ptB, +1, -1, c);
@@ -704,20 +725,19 @@ template <int EMF, typename S, class AW>
 __host__ __device__ __forceinline__ void edge_line_z(const PatchDev& P, int g, int i, int j0, int k,
                                                      int nj, const AW& w, S* out, int64_t ostride,
                                                      const Consts<S>& c) {
-  const uint32_t Nw = (uint32_t)P.Nwc;
   const uint32_t oy = (uint32_t)P.woff[1];
   uint32_t c0 = (uint32_t)wcell_of(P, g, i, j0, k) - 1u - oy;
   S pv[2][5], psa[2][5], psb[2][5];
-  corner_vals_pair<2>(w, c0, Nw, pv, psa, psb);
-  S pBA = w(c0 + 1u + W_BH * Nw), ptA = w(c0 + 1u + dbf_slot(0, 1) * Nw);
+  corner_vals_pair<2>(w, c0, pv, psa, psb);
+  S pBA = w.at(c0 + 1u, W_BH), ptA = w.at(c0 + 1u, dbf_slot(0, 1));
   for (int s = 0; s < nj; ++s) {
     c0 += oy;
     S v[2][5], sla[2][5], slb[2][5];
-    corner_vals_pair<2>(w, c0, Nw, v, sla, slb);
+    corner_vals_pair<2>(w, c0, v, sla, slb);
     S BB[2], tB[2];
-    w.pair(c0 + (W_BH + 1) * Nw, BB[0], BB[1]);
-    w.pair(c0 + dbf_slot(1, 0) * Nw, tB[0], tB[1]);
-    const S BA = w(c0 + 1u + W_BH * Nw), tA = w(c0 + 1u + dbf_slot(0, 1) * Nw);
+    w.pair_at(c0, W_BH + 1, BB[0], BB[1]);
+    w.pair_at(c0, dbf_slot(1, 0), tB[0], tB[1]);
+    const S BA = w.at(c0 + 1u, W_BH), tA = w.at(c0 + 1u, dbf_slot(0, 1));
     EdgeAcc<EMF, S> acc;
     acc.corner(0, pv[0], psa[0], psb[0], pBA, ptA, BB[0], tB[0], +1, +1, c);
     acc.corner(1, pv[1], psa[1], psb[1], pBA, ptA, BB[1], tB[1], -1, +1, c);
@@ -744,7 +764,7 @@ __host__ __device__ __forceinline__ void edge_line_item(const PatchDev& P, int g
   int L[3];
   edge_line_segments(P, L);
   const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-  const LdRel<T> w{S + P.wbase};
+  const LdRel<T> w{S + P.wbase, (uint32_t)P.Nwc};
   T* eb = S + P.sbase + 8 * P.Nc;
   const int seg = wave_uniform(item < L[0] ? 0 : item < L[0] + L[1] ? 1 : 2);
   if (seg == 0) {
@@ -817,13 +837,13 @@ template <typename T>
 __host__ __device__ __forceinline__ void face_flux_item(const PatchDev& P, int g, int d, int i, int j,
                                                         int k, const T* Win, const Consts<T>& c,
                                                         T F[5]) {
-  face_point(P, g, d, i, j, k, LdRel<T>{Win + P.wbase}, c, F);
+  face_point(P, g, d, i, j, k, LdRel<T>{Win + P.wbase, (uint32_t)P.Nwc}, c, F);
 }
 
 template <int EMF, typename T>
 __host__ __device__ __forceinline__ T edge_emf_item(const PatchDev& P, int g, int e, int i, int j, int k,
                                                     const T* Win, const Consts<T>& c) {
-  return edge_point<EMF>(P, g, e, i, j, k, LdRel<T>{Win + P.wbase}, c);
+  return edge_point<EMF>(P, g, e, i, j, k, LdRel<T>{Win + P.wbase, (uint32_t)P.Nwc}, c);
 }
 
 // -------------------------------------------------------------- time step
@@ -1039,7 +1059,7 @@ __host__ __device__ __forceinline__ T adj_w_item(const PatchDev& P, int g, const
                                                  const double* dxp, const Consts<T>& c) {
   typedef Dual<T> S;
   const Consts<S> cd = lift<S>(c);
-  const LdSeed<T> acc{W + P.wbase, (int64_t)v * P.Nwc + wcell_of(P, g, x[0], x[1], x[2])};
+  const LdSeed<T> acc{W + P.wbase, (int64_t)v * P.Nwc + wcell_of(P, g, x[0], x[1], x[2]), P.Nwc};
   const T dtdx[3] = {T(dt / dxp[0]), T(dt / dxp[1]), T(dt / dxp[2])};
   T sum = T(0);
   for (int d = 0; d < 3; ++d) {
@@ -1369,7 +1389,7 @@ __host__ __device__ __forceinline__ double solve_tile(X& ex, T* lds, const Patch
   const int64_t Nc = P.Nc;
   const T* u = Uin + P.ubase;
   T* uo = Uout + P.ubase;
-  const LdRel<T> wa{Win + P.wbase};
+  const LdRel<T> wa{Win + P.wbase, (uint32_t)P.Nwc};
   // time step of the next step: per direction, whether the tile's last cells sit at a domain
   // boundary (their upper face is then the exchange's copy of the last owned face)
   const bool cfl = nbr != nullptr;
