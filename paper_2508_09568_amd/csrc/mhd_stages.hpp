@@ -1052,7 +1052,26 @@ __host__ __device__ __forceinline__ T lam_emf(const PatchDev& P, int g, const T*
   return r;
 }
 
-// lambda_W[v] at predictor cell x: faces and edges that read it
+// Predictor slots a face normal to d reads (face_point): the half-step state of every
+// component but the normal field, the slopes along d, the half-step normal field.
+__host__ __device__ __forceinline__ bool face_reads_slot(int d, int v) {
+  if (v < 8) return v != 5 + d;
+  if (v < W_BH) return (v - W_SL) / 7 == d;
+  return v == W_BH + d;
+}
+// Predictor slots an edge along e reads (corner_state, at any of its corner cells): the
+// corner components, their slopes along the two transverse directions, the two transverse
+// half-step face fields and their transverse slopes.
+__host__ __device__ __forceinline__ bool edge_reads_slot(int e, int v) {
+  const int a = (e + 1) % 3, b = (e + 2) % 3;
+  const int comp[5] = {0, 1 + a, 1 + b, 4, 5 + e};
+  for (int t = 0; t < 5; ++t)
+    if (v == comp[t] || v == slope_slot(a, comp[t]) || v == slope_slot(b, comp[t])) return true;
+  return v == W_BH + a || v == W_BH + b || v == dbf_slot(a, b) || v == dbf_slot(b, a);
+}
+
+// lambda_W[v] at predictor cell x: faces and edges that read it (those that do not read slot
+// v have a zero derivative and are skipped)
 template <typename T>
 __host__ __device__ __forceinline__ T adj_w_item(const PatchDev& P, int g, const int x[3], int v,
                                                  const T* W, const T* lam, double dt,
@@ -1063,7 +1082,7 @@ __host__ __device__ __forceinline__ T adj_w_item(const PatchDev& P, int g, const
   const T dtdx[3] = {T(dt / dxp[0]), T(dt / dxp[1]), T(dt / dxp[2])};
   T sum = T(0);
   for (int d = 0; d < 3; ++d) {
-    if (!active(P, d)) continue;
+    if (!active(P, d) || !face_reads_slot(d, v)) continue;
     const int a = (d + 1) % 3, b = (d + 2) % 3;
     const int map[5] = {0, 1 + d, 1 + a, 1 + b, 4};
     for (int s = 0; s < 2; ++s) {
@@ -1076,6 +1095,7 @@ __host__ __device__ __forceinline__ T adj_w_item(const PatchDev& P, int g, const
     }
   }
   for (int e = 0; e < 3; ++e) {
+    if (!edge_reads_slot(e, v)) continue;
     const int a = (e + 1) % 3, b = (e + 2) % 3;
     for (int sb = 0; sb <= (active(P, b) ? 1 : 0); ++sb)
       for (int sa = 0; sa <= (active(P, a) ? 1 : 0); ++sa) {
@@ -1091,9 +1111,12 @@ __host__ __device__ __forceinline__ T adj_w_item(const PatchDev& P, int g, const
   return sum;
 }
 
-// sum over the predictor cells y within one cell of x (active directions) of
-// lambda_W(y) . dW(y)/d(seeded input), the seed given by the accessors
-template <typename T, class AU, class AQ, class AE>
+// sum over the predictor cells y that read the seeded input of lambda_W(y) . dW(y)/d(seed),
+// the seed given by the accessors.  pred_point at y reads the primitives and the face fields
+// at y and y +- e_d (slopes), and the time-n edge EMFs at y and y + e_d: with a seed at x the
+// cells that can read it are x and x -+ e_d (STENCIL 1, primitive or face-field seed) or x
+// and x - e_d (STENCIL 2, edge-EMF seed); the others have a zero derivative and are skipped.
+template <int STENCIL, typename T, class AU, class AQ, class AE>
 __host__ __device__ __forceinline__ T pred_gather(const PatchDev& P, int g, const int x[3],
                                                   const AU& u, const AQ& q, const AE& e,
                                                   const T* LW, double dt, const double* dxp,
@@ -1103,6 +1126,8 @@ __host__ __device__ __forceinline__ T pred_gather(const PatchDev& P, int g, cons
   for (int dz = -r2; dz <= r2; ++dz)
     for (int dy = -r1; dy <= r1; ++dy)
       for (int dx = -r0; dx <= r0; ++dx) {
+        if ((dx != 0) + (dy != 0) + (dz != 0) > 1) continue;  // only one direction off x
+        if (STENCIL == 2 && (dx > 0 || dy > 0 || dz > 0)) continue;
         const int y[3] = {x[0] + dx, x[1] + dy, x[2] + dz};
         if (!in_box(P, BOX_PRED, g, y)) continue;
         Dual<T> w[NW];
@@ -1140,7 +1165,7 @@ __host__ __device__ __forceinline__ T adj_e_item(const PatchDev& P, int g, const
                                                  const double* dxp, const Consts<T>& c) {
   const Consts<Dual<T>> cd = lift<Dual<T>>(c);
   const int64_t seed = P.sbase + 8 * P.Nc + (int64_t)k * P.Nc + cell_of(P, x[0], x[1], x[2]);
-  return pred_gather(P, g, x, LdSeed<T>{U, -1}, LdSeed<T>{S, -1}, LdSeed<T>{S, seed}, LW, dt, dxp, cd);
+  return pred_gather<2>(P, g, x, LdSeed<T>{U, -1}, LdSeed<T>{S, -1}, LdSeed<T>{S, seed}, LW, dt, dxp, cd);
 }
 
 // lambda_Q[m] at primitive cell x (read by the predictor and the edge EMFs at time n)
@@ -1151,7 +1176,7 @@ __host__ __device__ __forceinline__ T adj_q_item(const PatchDev& P, int g, const
   const Consts<Dual<T>> cd = lift<Dual<T>>(c);
   const int64_t seed = P.sbase + (int64_t)m * P.Nc + cell_of(P, x[0], x[1], x[2]);
   const LdSeed<T> qs{S, seed}, plainU{U, -1}, plainS{S, -1};
-  T sum = pred_gather(P, g, x, plainU, qs, plainS, LW, dt, dxp, cd);
+  T sum = pred_gather<1>(P, g, x, plainU, qs, plainS, LW, dt, dxp, cd);
   if (m >= 1 && m <= 3) sum = sum + en_gather(P, g, x, qs, plainU, LS);
   return sum;
 }
@@ -1168,7 +1193,7 @@ __host__ __device__ __forceinline__ T adj_u_item(const PatchDev& P, int g, const
   const LdSeed<T> us{U, seed}, plainS{S, -1};
   T sum = lam_out_at(P, g, lam, m, x);
   if (m >= 5) {
-    sum = sum + pred_gather(P, g, x, us, plainS, plainS, LW, dt, dxp, cd);
+    sum = sum + pred_gather<1>(P, g, x, us, plainS, plainS, LW, dt, dxp, cd);
     sum = sum + en_gather(P, g, x, plainS, us, LS);
   }
   // primitives of x and of the cell below in direction m-5 (cell-centred field average)
