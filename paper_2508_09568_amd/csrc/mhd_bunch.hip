@@ -531,8 +531,10 @@ __device__ __forceinline__ bool decode3(const PatchDev& P, int kind, int g, int 
   return decode(P, kind, g, first, x[0], x[1], x[2]);
 }
 
-template <typename T>
-__global__ __launch_bounds__(BLK) void k_adj_w(const PatchDev* __restrict__ pt,
+// lambda_W in two launches: PART 0 writes the faces' terms, PART 1 adds the edges' terms;
+// two waves per SIMD (the dual-number items spill at three)
+template <typename T, int EMF, int PART>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_w(const PatchDev* __restrict__ pt,
                                                const BoxBlock* __restrict__ blk, const T* __restrict__ S,
                                                T* __restrict__ LS, const T* __restrict__ lam,
                                                const double* __restrict__ dt,
@@ -543,8 +545,9 @@ __global__ __launch_bounds__(BLK) void k_adj_w(const PatchDev* __restrict__ pt,
   int x[3];
   if (!decode3(P, BOX_PRED, g, b.first, x)) return;
   const int v = blockIdx.y;
-  LS[P.wbase + (int64_t)v * P.Nwc + wcell_of(P, g, x[0], x[1], x[2])] =
-      adj_w_item(P, g, x, v, S, lam, dt[b.patch], dx + 3 * b.patch, c);
+  T& out = LS[P.wbase + (int64_t)v * P.Nwc + wcell_of(P, g, x[0], x[1], x[2])];
+  out = adj_w_item<EMF, PART>(P, g, x, v, S, lam, dt[b.patch], dx + 3 * b.patch, c,
+                              PART == 1 ? out : T(0));
 }
 
 template <typename T>
@@ -1181,9 +1184,18 @@ mhd_status launch_adjoint(mhd_bunch* h, const T* U, const T* lam, T* lam_in, con
                          h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], U, S, dt, dx,
                          (const double*)nullptr, c, h->g, ch.nblk[BOX_PRED], 0, (const int*)nullptr);
     // reverse sweep: predictor data, EMFs at t^n, primitives, padded input state
-    if (ch.nblk[BOX_PRED])
-      hipLaunchKernelGGL(k_adj_w<T>, dim3(ch.nblk[BOX_PRED], NW), dim3(BLK), 0, s, h->d_pt(),
-                         h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED], (const T*)S, LS, lam, dt, dx, c, h->g, 0);
+    if (ch.nblk[BOX_PRED]) {
+      const dim3 grid(ch.nblk[BOX_PRED], NW);
+      const BoxBlock* tb = h->d_blk(BOX_PRED) + ch.blk0[BOX_PRED];
+      hipLaunchKernelGGL((k_adj_w<T, 0, 0>), grid, dim3(BLK), 0, s, h->d_pt(), tb, (const T*)S, LS,
+                         lam, dt, dx, c, h->g, 0);
+      if (h->emf == 1)
+        hipLaunchKernelGGL((k_adj_w<T, 1, 1>), grid, dim3(BLK), 0, s, h->d_pt(), tb, (const T*)S,
+                           LS, lam, dt, dx, c, h->g, 0);
+      else
+        hipLaunchKernelGGL((k_adj_w<T, 0, 1>), grid, dim3(BLK), 0, s, h->d_pt(), tb, (const T*)S,
+                           LS, lam, dt, dx, c, h->g, 0);
+    }
     if (ch.nblk[BOX_EN])
       hipLaunchKernelGGL(k_adj_e<T>, dim3(ch.nblk[BOX_EN], 3), dim3(BLK), 0, s, h->d_pt(),
                          h->d_blk(BOX_EN) + ch.blk0[BOX_EN], U, (const T*)S, LS, dt, dx, c, h->g, 0);

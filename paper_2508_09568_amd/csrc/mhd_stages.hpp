@@ -1071,17 +1071,20 @@ __host__ __device__ __forceinline__ bool edge_reads_slot(int e, int v) {
 }
 
 // lambda_W[v] at predictor cell x: faces and edges that read it (those that do not read slot
-// v have a zero derivative and are skipped)
-template <typename T>
+// v have a zero derivative and are skipped).  PART 0: the faces' terms; PART 1: the edges'
+// terms added to sum0 (the faces' sum), in the order of one pass over both -- two launches
+// hold fewer registers than one (EMF: the edge solver, 0 UCT-HLL, 1 UCT-HLLD).
+template <int EMF, int PART, typename T>
 __host__ __device__ __forceinline__ T adj_w_item(const PatchDev& P, int g, const int x[3], int v,
                                                  const T* W, const T* lam, double dt,
-                                                 const double* dxp, const Consts<T>& c) {
+                                                 const double* dxp, const Consts<T>& c,
+                                                 T sum0 = T(0)) {
   typedef Dual<T> S;
   const Consts<S> cd = lift<S>(c);
   const LdSeed<T> acc{W + P.wbase, (int64_t)v * P.Nwc + wcell_of(P, g, x[0], x[1], x[2]), P.Nwc};
   const T dtdx[3] = {T(dt / dxp[0]), T(dt / dxp[1]), T(dt / dxp[2])};
-  T sum = T(0);
-  for (int d = 0; d < 3; ++d) {
+  T sum = sum0;
+  for (int d = 0; d < 3 && PART == 0; ++d) {
     if (!active(P, d) || !face_reads_slot(d, v)) continue;
     const int a = (d + 1) % 3, b = (d + 2) % 3;
     const int map[5] = {0, 1 + d, 1 + a, 1 + b, 4};
@@ -1094,7 +1097,7 @@ __host__ __device__ __forceinline__ T adj_w_item(const PatchDev& P, int g, const
       for (int t = 0; t < 5; ++t) sum = sum + lam_flux(P, g, lam, d, map[t], f, dtdx[d]) * F[t].d;
     }
   }
-  for (int e = 0; e < 3; ++e) {
+  for (int e = 0; e < 3 && PART == 1; ++e) {
     if (!edge_reads_slot(e, v)) continue;
     const int a = (e + 1) % 3, b = (e + 2) % 3;
     for (int sb = 0; sb <= (active(P, b) ? 1 : 0); ++sb)
@@ -1103,8 +1106,7 @@ __host__ __device__ __forceinline__ T adj_w_item(const PatchDev& P, int g, const
         y[a] += sa;
         y[b] += sb;
         if (!edge_computed(P, g, e, y)) continue;
-        const S em = c.emf == 1 ? edge_point<1>(P, g, e, y[0], y[1], y[2], acc, cd)
-                                : edge_point<0>(P, g, e, y[0], y[1], y[2], acc, cd);
+        const S em = edge_point<EMF>(P, g, e, y[0], y[1], y[2], acc, cd);
         sum = sum + lam_emf(P, g, lam, e, y, dtdx) * em.d;
       }
   }
