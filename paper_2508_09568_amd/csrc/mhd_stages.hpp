@@ -1140,15 +1140,19 @@ __host__ __device__ __forceinline__ T pred_gather(const PatchDev& P, int g, cons
   return sum;
 }
 
-// sum over the edge-EMF cells y within one cell of x of lambda_E(y) . dE(y)/d(seed)
+// sum over the edge-EMF cells y that read the seeded input of lambda_E(y) . dE(y)/d(seed): the
+// EMFs of cell y read the primitives of y, y - e_a, y - e_b, y - e_a - e_b and the face fields
+// of y, y - e_a, y - e_b (a, b transverse), so a seed at x is read from y = x + o with o in
+// {0, 1}^3 and not all three directions set
 template <typename T, class AQ, class AU>
 __host__ __device__ __forceinline__ T en_gather(const PatchDev& P, int g, const int x[3], const AQ& q,
                                                 const AU& u, const T* LS) {
   T sum = T(0);
   const int r0 = active(P, 0), r1 = active(P, 1), r2 = active(P, 2);
-  for (int dz = -r2; dz <= r2; ++dz)
-    for (int dy = -r1; dy <= r1; ++dy)
-      for (int dx = -r0; dx <= r0; ++dx) {
+  for (int dz = 0; dz <= r2; ++dz)
+    for (int dy = 0; dy <= r1; ++dy)
+      for (int dx = 0; dx <= r0; ++dx) {
+        if (dx + dy + dz == 3) continue;
         const int y[3] = {x[0] + dx, x[1] + dy, x[2] + dz};
         if (!in_box(P, BOX_EN, g, y)) continue;
         Dual<T> E[3];
@@ -1198,11 +1202,13 @@ __host__ __device__ __forceinline__ T adj_u_item(const PatchDev& P, int g, const
     sum = sum + pred_gather<1>(P, g, x, us, plainS, plainS, LW, dt, dxp, cd);
     sum = sum + en_gather(P, g, x, plainS, us, LS);
   }
-  // primitives of x and of the cell below in direction m-5 (cell-centred field average)
+  // primitives of x and of the cell below in direction m-5 (cell-centred field average; the
+  // primitives of y read the fields of y and the face fields of y + e_d)
   const int r0 = active(P, 0), r1 = active(P, 1), r2 = active(P, 2);
   for (int dz = -r2; dz <= 0; ++dz)
     for (int dy = -r1; dy <= 0; ++dy)
       for (int dx = -r0; dx <= 0; ++dx) {
+        if ((dx != 0) + (dy != 0) + (dz != 0) > 1) continue;
         const int y[3] = {x[0] + dx, x[1] + dy, x[2] + dz};
         if (!in_box(P, BOX_PRIM, g, y)) continue;
         Dual<T> q[8];
