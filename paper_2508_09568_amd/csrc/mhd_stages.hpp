@@ -171,8 +171,17 @@ struct LdRel {
 // The same loads with the slot's base formed apart from the cell: the base is uniform across
 // the wavefront (scalar registers) and the cell's byte offset is shared by every slot read at
 // that cell, so a load spends no vector instruction on its address beyond the offset of its
-// cell.  Used by the edge lines (in FP32 3 % faster there; in the solver tile's faces the
-// extra scalar bases cost more than they save).
+// cell.  Used by the FP32 edge lines (3 % faster there; no gain measured in FP64 or in the
+// solver tile's faces, whose scalar registers are tight).
+template <bool C, class A, class B>
+struct Pick {
+  typedef A type;
+};
+template <class A, class B>
+struct Pick<false, A, B> {
+  typedef B type;
+};
+
 template <typename T>
 struct LdSlot {
   const T* p;
@@ -777,7 +786,9 @@ __host__ __device__ __forceinline__ void edge_line_item(const PatchDev& P, int g
   int L[3];
   edge_line_segments(P, L);
   const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-  const LdSlot<T> w{S + P.wbase, (uint32_t)P.Nwc};
+  // FP32: slot-based loads (3 % faster); FP64: the combined index (no gain measured)
+  typedef typename Pick<sizeof(T) == 4, LdSlot<T>, LdRel<T>>::type Acc;
+  const Acc w{S + P.wbase, (uint32_t)P.Nwc};
   T* eb = S + P.sbase + 8 * P.Nc;
   const int seg = wave_uniform(item < L[0] ? 0 : item < L[0] + L[1] ? 1 : 2);
   if (seg == 0) {
