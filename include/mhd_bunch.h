@@ -350,7 +350,7 @@ enum {
   MHD_KERNEL_SOLVE = 3,       /* HLLD fluxes, edge EMFs (forms 0, 1), update */
   MHD_KERNEL_CFL = 4,         /* time step (three small kernels, timed together) */
   MHD_KERNEL_GUARDS = 5,      /* guard fill */
-  MHD_KERNEL_EDGE = 6,        /* half-step edge EMFs (solver form 2) */
+  MHD_KERNEL_EDGE = 6,        /* half-step edge EMFs (solver forms 2, 3) */
   MHD_KERNEL_COUNT = 7
 };
 mhd_status mhd_bunch_profile(mhd_bunch* h, int32_t enable);

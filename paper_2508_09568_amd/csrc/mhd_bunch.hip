@@ -9,9 +9,11 @@
 //   predictor, fused (modes >= 1): k_predict does the three steps per 3D tile, with the
 //               tile's primitives and face fields in shared memory and the edge EMFs at
 //               time n evaluated from them where they are read
-//   k_edges   : (solver form 2 only) half-step edge EMFs, each edge once, into scratch
+//   k_edges   : (solver form 2) half-step edge EMFs, each edge once, into scratch
+//   k_edge_lines: (solver form 3, 3D bunches) the same EMFs as lines of edges, one thread
+//               stepping along each line
 //   k_solve   : per 3D tile, HLLD on every face and the four-state EMF on every edge (or
-//               the EMFs k_edges left) into shared memory, then the conservative +
+//               the EMFs the edge pass left) into shared memory, then the conservative +
 //               constrained-transport update.
 // Side kernels: k_cfl / k_cfl_final (per-patch time step, wavefront max-reduction + one
 // 64-bit atomic per work-group), k_guards (guard fill from a neighbour table), the local
@@ -928,7 +930,8 @@ void edges_launch(mhd_bunch* h, int nt, const TileDev* tl, T* S, const double* d
                      h->d_pt(), tl, S, dt, dx, c, h->g, nt, h->mode >= 1 || dcount, dcount);
 }
 
-// edges = true: the owned-edge pass of solver form 2; else the solver tiles
+// edges = true: the per-tile owned-edge pass (solver form 2, and form 3 outside 3D); else the
+// solver tiles
 template <typename T>
 void launch_solve(mhd_bunch* h, const mhd_bunch::Chunk& ch, const T* Uin, T* Uout, T* S,
                   const double* dt, const double* dx, const Consts<T>& c, hipStream_t s,
