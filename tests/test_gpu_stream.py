@@ -28,25 +28,35 @@ def _state(name):
     return L, U, np.ascontiguousarray(dx), dt, gam, prm
 
 
-@pytest.mark.parametrize("name,per,slots,precision", [("turb", 7, 3, 8), ("turb", 16, 1, 8),
-                                                      ("turb", 5, 2, 4), ("ragged", 2, 3, 8)])
-def test_streamed_update_matches_resident_update(name, per, slots, precision):
+@pytest.mark.parametrize("name,per,slots,precision,cfg", [("turb", 7, 3, 8, None), ("turb", 16, 1, 8, None),
+                                                          ("turb", 5, 2, 4, None), ("ragged", 2, 3, 8, None),
+                                                          ("turb", 7, 3, 8, (1, 1, 3)),
+                                                          ("ragged", 3, 2, 4, (4, 2, 3))])
+def test_streamed_update_matches_resident_update(name, per, slots, precision, cfg):
+    """cfg: (tile configuration, predictor mode, solver form) of every sub-bunch and of the
+    resident bunch; None keeps the defaults."""
     import oracle
     import torch
 
     from paper_2508_09568_amd.binding import Stream
-    log(f"[gpu] streamed update {name} per={per} slots={slots} precision={precision}")
+    log(f"[gpu] streamed update {name} per={per} slots={slots} precision={precision} cfg={cfg}")
     L, U, dx, dt, gam, prm = _state(name)
     dty = torch.float64 if precision == 8 else torch.float32
     Uh = torch.as_tensor(U).to(dty).pin_memory()
     Uo = torch.full_like(Uh, float("nan")).pin_memory()
     S = Stream(L.dims, per, slots=slots, precision=precision, gamma=gam)
+    if cfg is not None:
+        S.configure(*cfg)
     assert S.bunches() == (L.P + per - 1) // per
     S.update(Uh, Uo, torch.as_tensor(dt), torch.as_tensor(np.ascontiguousarray(dx).ravel()))
     assert S.check() == 0
     got = Uo.double().numpy()
     # resident update of the same state
     B = make_bunch(L, gam, precision=precision)
+    if cfg is not None:
+        B.set_tile(cfg[0])
+        B.set_predictor(cfg[1])
+        B.set_solver_split(cfg[2])
     Ud = Uh.to("cuda")
     Ur = torch.zeros_like(Ud)
     B.update(Ud, Ur, dev(dt), dev(dx))
