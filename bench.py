@@ -44,6 +44,7 @@ MEASURED_TRAFFIC = {
     "bytes_per_update": {
         "[32, 4, 2, 1]/1/3": 234.06e9,
         "[32, 8, 2, 1]/1/3": 229.05e9,
+        "[32, 4, 4, 1]/1/3": 229.34e9,
     },
     "profile": "profiles/mhd_update_turbulence512_pmc.md",
 }
