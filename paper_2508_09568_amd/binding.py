@@ -354,7 +354,8 @@ class Bunch:
         return out
 
     def set_solver_split(self, form):
-        """Solver form: 0 one-phase tile, 1 two-phase tile, 2 separate edge-EMF pass."""
+        """Solver form: 0 one-phase tile, 1 two-phase tile, 2 separate edge-EMF pass, 3 that
+        pass as lines of edges (3D bunches; form 2 otherwise)."""
         _ok(mhd_bunch_set_solver_split(self._h, int(form)), "mhd_bunch_set_solver_split")
 
     def solver_split(self):
