@@ -334,11 +334,12 @@ def run_batched(steps, steps_per_patch):
     }
 
 
-def run_lts(w, tile, t_mult):
+def run_lts(w, tile, t_mult, own_only=False):
     """Local time stepping on the benchmark workload (FP64, the tuned launch configuration) to
     t_end = t_mult x the largest power of two not above the smallest patch CFL step, against
     global stepping (guard exchange + global CFL + update) to the same time.  Wall time
-    includes the host reading the times."""
+    includes the host reading the times.  With own_only, only the eager run with each patch's
+    own CFL step (for a kernel trace of its steps)."""
     import numpy as np
     import torch
 
@@ -361,6 +362,17 @@ def run_lts(w, tile, t_mult):
     quantum = 2.0 ** np.floor(np.log2(float(own.min())))
     t_end = t_mult * quantum
     cells = int(np.prod(L.dims[0]))
+    if own_only:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Ul, tl, nl, cnt = lts.run(B, U, dx, nbr, t_end, check_every=8)
+        torch.cuda.synchronize()
+        wall_l = time.perf_counter() - t0
+        if B.check() != 0:
+            raise RuntimeError("device status after the local-time-stepping run")
+        upd_l = int(cnt.sum().item()) * cells
+        return {"t_end": t_end, "lts": {"steps": nl, "cell_updates": upd_l, "ms": 1e3 * wall_l,
+                                        "cell_updates_per_s": upd_l / wall_l}}
     # global stepping
     Ua, Ub = U.clone(), torch.empty_like(U)
     torch.cuda.synchronize()
@@ -678,6 +690,10 @@ def main():
                     help="skip the local-time-stepping run")
     ap.add_argument("--lts-span", type=float, default=8.0,
                     help="local-time-stepping run to this many smallest patch CFL steps")
+    ap.add_argument("--lts-only", action="store_true",
+                    help="only the FP64 local-time-stepping run with each patch's own CFL step "
+                         "(eager launches, for a kernel trace), in the launch configuration "
+                         "--tile / --predictor / --split, then exit")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run 5 plain device-to-device copies of this many bytes (HBM "
                          "counter calibration under rocprofv3 --pmc) and exit")
@@ -715,6 +731,17 @@ def main():
                               oracle.Params(gamma=w.gamma))
     flops = float(ops[:4].sum())
 
+    if args.lts_only:
+        from paper_2508_09568_amd.binding import Bunch
+        if args.tile is None or args.predictor is None or args.split is None:
+            sys.exit("--lts-only needs --tile, --predictor and --split")
+        L = w.layout
+        cfgs = Bunch(L.dims, g=L.g, precision=8, gamma=w.gamma, cfl=w.cfl).tile_configs()
+        tile = {"chosen": list(cfgs[args.tile]), "fused_predictor": args.predictor,
+                "solver_split": args.split}
+        res = run_lts(w, tile, args.lts_span, own_only=True)
+        print(json.dumps({"lts_only": res, "tile": tile}), flush=True)
+        return
     if args.fp32_only:
         r32 = run_precision(w, 4, args.steps, args.warmup, flops, args.tile, args.predictor,
                             args.split)
