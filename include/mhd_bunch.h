@@ -123,8 +123,9 @@ mhd_status mhd_bunch_cfl(mhd_bunch* h, const void* U_dev, const double* dx_dev,
 
 /* One step of local time stepping (§2.2 "DISPATCH": every patch carries time slices and
  * advances with its own time step; §3.1 "DISPATCH Validation": guard zones are interpolated
- * between asynchronous patch times).  Device arrays: three state buffers (U_cur at times
- * t[p], U_prev at t_prev[p], U_new), t[P], t_prev[P], dt[P] (written), dt_fixed[P] or NULL,
+ * between asynchronous patch times).  Device arrays: two state buffers (U_cur at times
+ * t[p], U_prev at t_prev[p]; U_new is not accessed and may be NULL: the update runs in place),
+ * t[P], t_prev[P], dt[P] (written), dt_fixed[P] or NULL,
  * dx[P][3], nbr[P][27] as for mhd_bunch_fill_guards.  On the stream, in order:
  *  1. ready[p] = t[p] < t_end and no neighbour q (any of the 26 entries) has t[q] < t[p];
  *  2. the guards of every ready patch p in U_cur are filled at its time t[p]: the owner q's
@@ -134,21 +135,22 @@ mhd_status mhd_bunch_cfl(mhd_bunch* h, const void* U_dev, const double* dx_dev,
  *     own CFL step, rounded down to dt_quantum x 2^k (k any integer) when dt_quantum > 0 (time
  *     levels: patches then advance in lock-step groups, fewer steps per run; take a power
  *     of two, so that the times of a level are exact sums);
- *  4. the ready patches are updated from U_cur into U_new (scratch: patches at rest are
- *     neither computed nor written);
- *  5. for every ready patch: U_prev <- U_cur (its whole padded block), then U_cur's owned
- *     cells and faces <- U_new's, t_prev[p] = t[p], t[p] += dt[p] (exactly t_end when the
- *     step was clipped to it).
+ *  4. the ready patches are updated in place: U_prev's owned cells and faces <- U_cur's,
+ *     U_cur's owned cells and faces <- their update (patches at rest are neither computed
+ *     nor written; U_prev's guard cells are never written: the guard fill reads owned
+ *     values only);
+ *  5. for every ready patch: t_prev[p] = t[p], t[p] += dt[p] (exactly t_end when the step
+ *     was clipped to it).
  * With free steps (dt_quantum == 0) and a bunch processed in one chunk (no scratch cap) the
- * launches of steps 2-5 run over device-compacted tables of the ready patches' entries
+ * launches of steps 2-4 run over device-compacted tables of the ready patches' entries
  * (persistent grids), so a step costs in proportion to the patches that advance; with time
  * levels (most patches advance together) they run over the full tables.
  * A ready patch whose step (given or its own CFL step) is not finite and > 0 gets dt[p] = 0,
  * stays where it is and raises a status bit that mhd_bunch_check reports as MHD_EINVAL.
  * On return U_cur holds every patch at its time t[p] (no buffers to swap).  Start with
  * t = t_prev (one slice per patch) and U_prev any buffer of the right size.  The run is over
- * when every t[p] == t_end.  The three
- * state buffers must not overlap, t, t_prev, dt and dt_fixed must be distinct, dt_fixed must
+ * when every t[p] == t_end.  The state
+ * buffers (U_new if given) must not overlap, t, t_prev, dt and dt_fixed must be distinct, dt_fixed must
  * hold finite steps > 0 and dt_quantum must be finite and >= 0 (MHD_EINVAL).  Only kernels are enqueued (no host synchronisation, no
  * memset or copy calls). */
 mhd_status mhd_bunch_lts_step(mhd_bunch* h, void* U_cur, void* U_new, void* U_prev, double* t_dev,

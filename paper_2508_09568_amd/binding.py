@@ -153,6 +153,10 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _optr(t):
+    return None if t is None else _ptr(t)
+
+
 def _stream(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -395,17 +399,19 @@ class Bunch:
         """One local time step (see include/mhd_bunch.h): ready patches fill their guards at
         their own time from the owners' two slices and advance by their own CFL step (or
         dt_fixed; rounded down to dt_quantum x 2^k if dt_quantum > 0) clipped to t_end; the
-        others stay.  t, t_prev and dt (written) are (P,) float64 device tensors.  U_new is
-        scratch; on return U_cur holds every patch at its own time."""
+        others stay.  t, t_prev and dt (written) are (P,) float64 device tensors.  The update
+        runs in place: U_new is not used (None, or any state tensor); on return U_cur holds
+        every patch at its own time and U_prev the owned values of its previous slice."""
         for x, what in ((U_cur, "U_cur"), (U_new, "U_new"), (U_prev, "U_prev")):
-            self._check_state(x, what)
+            if x is not None or what != "U_new":
+                self._check_state(x, what)
         for x, what in ((t, "t"), (t_prev, "t_prev"), (dt, "dt")):
             self._check_dt_named(x, what)
         if dt_fixed is not None:
             self._check_dt_named(dt_fixed, "dt_fixed")
         self._check_dx(dx)
         self._check_nbr(nbr)
-        _ok(mhd_bunch_lts_step(self._h, _ptr(U_cur), _ptr(U_new), _ptr(U_prev), _ptr(t),
+        _ok(mhd_bunch_lts_step(self._h, _ptr(U_cur), _optr(U_new), _ptr(U_prev), _ptr(t),
                                _ptr(t_prev), _ptr(dt), None if dt_fixed is None else _ptr(dt_fixed),
                                _ptr(dx), _ptr(nbr), float(t_end), float(dt_quantum),
                                _stream(stream)),
@@ -416,7 +422,8 @@ class Bunch:
         """Capture nsteps local time steps (arguments as lts_step) in the handle's HIP graph;
         graph_launch runs them."""
         for x, what in ((U_cur, "U_cur"), (U_new, "U_new"), (U_prev, "U_prev")):
-            self._check_state(x, what)
+            if x is not None or what != "U_new":
+                self._check_state(x, what)
         for x, what in ((t, "t"), (t_prev, "t_prev"), (dt, "dt")):
             self._check_dt_named(x, what)
         if dt_fixed is not None:
@@ -424,7 +431,7 @@ class Bunch:
         self._check_dx(dx)
         self._check_nbr(nbr)
         self._graph_refs = (U_cur, U_new, U_prev, t, t_prev, dt, dt_fixed, dx, nbr)
-        _ok(mhd_bunch_lts_graph_capture(self._h, int(nsteps), _ptr(U_cur), _ptr(U_new),
+        _ok(mhd_bunch_lts_graph_capture(self._h, int(nsteps), _ptr(U_cur), _optr(U_new),
                                         _ptr(U_prev), _ptr(t), _ptr(t_prev), _ptr(dt),
                                         None if dt_fixed is None else _ptr(dt_fixed), _ptr(dx),
                                         _ptr(nbr), float(t_end), float(dt_quantum),

@@ -17,8 +17,8 @@
 //               constrained-transport update.
 // Side kernels: k_cfl / k_cfl_final (per-patch time step, wavefront max-reduction + one
 // 64-bit atomic per work-group), k_guards (guard fill from a neighbour table), the local
-// time stepping step (k_lts_ready, k_guards_at, k_lts_dt, k_lts_keep, k_lts_time around
-// the update), and the k_adj_* reverse sweep of the adjoint, which re-runs the staged
+// time stepping step (k_lts_ready, k_guards_at, k_lts_dt and k_lts_time around the update,
+// which runs in place and writes the previous slice), and the k_adj_* reverse sweep of the adjoint, which re-runs the staged
 // predictor kernels first.  Patches with dt = 0 are copied by the update, not computed.
 #include <hip/hip_runtime.h>
 
@@ -178,6 +178,28 @@ __attribute__((amdgpu_waves_per_eu(SolveWaves<T, TX, TY, TZ, FORM>::value))) voi
         atomicMax(cfl_max + tl.patch, (unsigned long long)__double_as_longlong(m));
       }
     }
+    ex.sync();  // the next tile reuses the shared memory
+  }
+}
+
+// The update of local time stepping: in place (U is read and written; each cell's state is
+// read before it is written and no tile reads another's cells) with the previous state of
+// every updated cell written to keep; patches at rest (dt = 0) are skipped.
+template <typename T, int TX, int TY, int TZ, int FORM, int EMF>
+__global__ __launch_bounds__((TileShape<TX, TY, TZ>::THREADS))
+__attribute__((amdgpu_waves_per_eu(SolveWaves<T, TX, TY, TZ, FORM>::value))) void k_solve_keep(
+    const PatchDev* __restrict__ pt, const TileDev* __restrict__ tiles, T* U,
+    T* __restrict__ keep, const T* __restrict__ S, const double* __restrict__ dt,
+    const double* __restrict__ dx, Consts<T> c, int g, int ntile0, int remap,
+    const int* __restrict__ dcount) {
+  __shared__ T lds[TileShape<TX, TY, TZ>::template Lds<FORM>::value];
+  DevX ex;
+  const int ntile = table_count(ntile0, dcount);
+  for (int vb = blockIdx.x; vb < ntile; vb += gridDim.x) {
+    const TileDev tl = tiles[logical_block(vb, ntile, remap)];
+    if (dt[tl.patch] == 0.0) continue;
+    solve_tile<T, TX, TY, TZ, FORM, EMF, true>(ex, lds, pt[tl.patch], g, tl, U, U, S, dt[tl.patch],
+                                               dx + 3 * tl.patch, c, nullptr, tl.patch, keep);
     ex.sync();  // the next tile reuses the shared memory
   }
 }
@@ -383,31 +405,6 @@ __global__ __launch_bounds__(BLK) void k_lts_dt(int32_t* __restrict__ ready,
     ready[p] = 0;
   }
   dt[p] = r && good ? (d < rest ? d : rest) : 0.0;
-}
-
-// every ready patch: previous slice <- its state before the step (all padded cells), then
-// its owned values <- the update's result (patches at rest are touched by neither)
-template <typename T>
-__global__ __launch_bounds__(BLK) void k_lts_keep(const PatchDev* __restrict__ pt,
-                                                  const BoxBlock* __restrict__ blk, T* U,
-                                                  const T* __restrict__ Unew, T* __restrict__ Uprev,
-                                                  const int32_t* __restrict__ ready, int g,
-                                                  int nb0, const int* __restrict__ dcount) {
-  const int nb = table_count(nb0, dcount);
-  for (int vb = blockIdx.x; vb < nb; vb += gridDim.x) {
-    const BoxBlock b = blk[vb];
-    if (!ready[b.patch]) continue;
-    const PatchDev& P = pt[b.patch];
-    int x[3];
-    if (!decode(P, BOX_ALL, g, b.first, x[0], x[1], x[2])) continue;
-    const int64_t cell = cell_of(P, x[0], x[1], x[2]);
-    const bool own = owned(P, g, x);
-    for (int m = 0; m < 8; ++m) {
-      const int64_t e = P.ubase + m * P.Nc + cell;
-      Uprev[e] = U[e];
-      if (own) U[e] = Unew[e];
-    }
-  }
 }
 
 // time of every ready patch advances by its step; a step clipped to t_end ends exactly there
@@ -776,6 +773,9 @@ struct mhd_bunch {
   const void* ctab(int id) const { return ws + o_ctab[id]; }
   const int* ccount(int id) const { return (const int*)(ws + o_total) + cslot[id]; }
   bool copy_rest = true;  // update: copy patches at rest (false inside a local time step)
+  // inside a local time step: the update runs in place and the solver tiles write each
+  // updated cell's previous state here (the previous time slice)
+  void* keep = nullptr;
   size_t o_pt = 0, o_blk[NBOX] = {0}, o_tiles[MAXSHAPE] = {0}, o_smax = 0, o_status = 0,
          o_scratch = 0;
   // mhd_bunch_graph_capture: instantiated graph of a multi-step run
@@ -901,17 +901,25 @@ void solve_launch(mhd_bunch* h, int nt, const TileDev* tl, const T* Uin, T* Uout
                   const double* dt, const double* dx, const Consts<T>& c, hipStream_t s,
                   const int* dcount) {
   int grid = nt;
+  const void* kern = h->keep ? reinterpret_cast<const void*>(k_solve_keep<T, X, Y, Z, FORM, EMF>)
+                             : reinterpret_cast<const void*>(k_solve<T, X, Y, Z, FORM, EMF>);
   if (h->mode == 2 || dcount) {
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void*>(k_solve<T, X, Y, Z, FORM, EMF>),
-            TileShape<X, Y, Z>::THREADS, 0) != hipSuccess || occ < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, TileShape<X, Y, Z>::THREADS, 0) !=
+            hipSuccess ||
+        occ < 1)
       occ = 1;
     grid = h->persistent_grid(nt, occ);
   }
-  hipLaunchKernelGGL((k_solve<T, X, Y, Z, FORM, EMF>), dim3(grid), dim3(TileShape<X, Y, Z>::THREADS), 0,
-                     s, h->d_pt(), tl, Uin, Uout, S, dt, dx, c, h->g, nt, h->mode >= 1 || dcount,
-                     h->copy_rest ? 1 : 0, dcount, h->cfl_next, h->cfl_nbr);
+  if (h->keep)  // in place (Uin == Uout), no fused time step, patches at rest skipped
+    hipLaunchKernelGGL((k_solve_keep<T, X, Y, Z, FORM, EMF>), dim3(grid),
+                       dim3(TileShape<X, Y, Z>::THREADS), 0, s, h->d_pt(), tl, Uout, (T*)h->keep,
+                       S, dt, dx, c, h->g, nt, h->mode >= 1 || dcount, dcount);
+  else
+    hipLaunchKernelGGL((k_solve<T, X, Y, Z, FORM, EMF>), dim3(grid),
+                       dim3(TileShape<X, Y, Z>::THREADS), 0, s, h->d_pt(), tl, Uin, Uout, S, dt,
+                       dx, c, h->g, nt, h->mode >= 1 || dcount, h->copy_rest ? 1 : 0, dcount,
+                       h->cfl_next, h->cfl_nbr);
 }
 
 template <typename T, int X, int Y, int Z, int EMF>
@@ -1220,7 +1228,7 @@ mhd_status launch_adjoint(mhd_bunch* h, const T* U, const T* lam, T* lam_in, con
 }
 
 template <typename T>
-mhd_status launch_lts_step(mhd_bunch* h, T* Ucur, T* Unew, T* Uprev, double* t, double* tprev,
+mhd_status launch_lts_step(mhd_bunch* h, T* Ucur, T* Uprev, double* t, double* tprev,
                            double* dt, const double* dt_fixed, const double* dx,
                            const int32_t* nbr, double t_end, double quantum, hipStream_t s) {
   const int pg = (h->P + BLK - 1) / BLK;
@@ -1247,7 +1255,6 @@ mhd_status launch_lts_step(mhd_bunch* h, T* Ucur, T* Unew, T* Uprev, double* t, 
     };
     for (int id = 0; id < mhd_bunch::NTAB; ++id) h->cslot[id] = -1;
     add(BOX_GUARD, 1);
-    add(BOX_ALL, 1);
     if (!dt_fixed) add(BOX_INTERIOR, 1);
     add(NBOX + h->shape, 2);
     if (h->split == 3 && h->act == 7) add(BOX_LINE, 1);
@@ -1282,17 +1289,16 @@ mhd_status launch_lts_step(mhd_bunch* h, T* Ucur, T* Unew, T* Uprev, double* t, 
     hipLaunchKernelGGL(k_lts_dt, dim3(pg), dim3(BLK), 0, s, ready, (const double*)t,
                        t_end, quantum, dt_fixed ? dt_fixed : (const double*)dt, dt, h->P,
                        h->d_status());
-    h->copy_rest = false;  // U_new is scratch: only the ready patches' results are kept
-    st = launch_update<T>(h, (const T*)Ucur, Unew, dt, dx, s, (T*)h->d_scratch());
+    // the ready patches advance in place; their solver tiles write each cell's state before
+    // the update to U_prev (owned cells and faces: the previous slice); patches at rest are
+    // neither computed nor written
+    h->copy_rest = false;
+    h->keep = Uprev;
+    st = launch_update<T>(h, (const T*)Ucur, Ucur, dt, dx, s, (T*)h->d_scratch());
+    h->keep = nullptr;
     h->copy_rest = true;
   }
   if (st == MHD_OK) {
-    const int na = (int)h->blocks[BOX_ALL].size();
-    hipLaunchKernelGGL(k_lts_keep<T>, dim3(cmp ? h->persistent_grid(na, 2048 / BLK) : na),
-                       dim3(BLK), 0, s, h->d_pt(),
-                       cmp ? (const BoxBlock*)h->ctab(BOX_ALL) : h->d_blk(BOX_ALL), Ucur,
-                       (const T*)Unew, Uprev, (const int32_t*)ready, h->g, na,
-                       cmp ? h->ccount(BOX_ALL) : nullptr);
     hipLaunchKernelGGL(k_lts_time, dim3(pg), dim3(BLK), 0, s, (const int32_t*)ready, t, tprev,
                        (const double*)dt, t_end, h->P);
   }
@@ -1796,21 +1802,21 @@ mhd_status mhd_bunch_lts_step(mhd_bunch* h, void* U_cur, void* U_new, void* U_pr
                               double* t_prev, double* dt, const double* dt_fixed,
                               const double* dx, const int32_t* nbr, double t_end,
                               double dt_quantum, hipStream_t s) {
-  if (!h || !U_cur || !U_new || !U_prev || !t || !t_prev || !dt || !dx || !nbr) return MHD_EINVAL;
+  if (!h || !U_cur || !U_prev || !t || !t_prev || !dt || !dx || !nbr) return MHD_EINVAL;
   if (!(t_end == t_end) || t == t_prev || dt == t || dt == t_prev) return MHD_EINVAL;
   if (dt_fixed && (dt_fixed == dt || dt_fixed == t || dt_fixed == t_prev)) return MHD_EINVAL;
   if (!(dt_quantum >= 0.0) || dt_quantum > 1e300) return MHD_EINVAL;
   if (!h->bound) return MHD_ESTATE;
   const size_t bytes = (size_t)h->state_elems * h->prec;
-  const char* b[3] = {(const char*)U_cur, (const char*)U_new, (const char*)U_prev};
+  const char* b[3] = {(const char*)U_cur, (const char*)U_prev, (const char*)U_new};
   for (int x = 0; x < 3; ++x)
     for (int y = x + 1; y < 3; ++y)
-      if (b[x] < b[y] + bytes && b[y] < b[x] + bytes) return MHD_EINVAL;
+      if (b[x] && b[y] && b[x] < b[y] + bytes && b[y] < b[x] + bytes) return MHD_EINVAL;
   return h->prec == 8
-             ? launch_lts_step<double>(h, (double*)U_cur, (double*)U_new, (double*)U_prev, t,
-                                       t_prev, dt, dt_fixed, dx, nbr, t_end, dt_quantum, s)
-             : launch_lts_step<float>(h, (float*)U_cur, (float*)U_new, (float*)U_prev, t, t_prev,
-                                      dt, dt_fixed, dx, nbr, t_end, dt_quantum, s);
+             ? launch_lts_step<double>(h, (double*)U_cur, (double*)U_prev, t, t_prev, dt,
+                                       dt_fixed, dx, nbr, t_end, dt_quantum, s)
+             : launch_lts_step<float>(h, (float*)U_cur, (float*)U_prev, t, t_prev, dt, dt_fixed,
+                                      dx, nbr, t_end, dt_quantum, s);
 }
 
 mhd_status mhd_bunch_check(mhd_bunch* h, hipStream_t s) {

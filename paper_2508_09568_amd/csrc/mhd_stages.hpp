@@ -1395,12 +1395,17 @@ __host__ __device__ __forceinline__ void copy_tile(X& ex, const PatchDev& P, int
 // with a neighbour patch it is the value that patch's update writes there (the same EMFs,
 // the same dt); at a domain boundary (nbr entry -1) the exchange copies the last owned face.
 // Otherwise it returns 0.
-template <typename T, int TX, int TY, int TZ, int FORM, int EMF, class X>
+// KEEP: each cell's state is read before any of it is written and no other cell of Uin is
+// read (nbr must be nullptr), so the update may run in place (Uout == Uin), and the cell's
+// state before the update is also written to keep (the previous time slice of local time
+// stepping: owned cells and faces).
+template <typename T, int TX, int TY, int TZ, int FORM, int EMF, bool KEEP = false, class X>
 __host__ __device__ __forceinline__ double solve_tile(X& ex, T* lds, const PatchDev& P, int g,
                                                     const TileDev& tl, const T* Uin, T* Uout,
                                                     const T* Win, double dt, const double* dxp,
                                                     const Consts<T>& c,
-                                                    const int32_t* nbr = nullptr, int patch = 0) {
+                                                    const int32_t* nbr = nullptr, int patch = 0,
+                                                    T* keep = nullptr) {
   using SH = TileShape<TX, TY, TZ>;
   T* fx = lds;
   T* fy = fx + 5 * SH::NFX;
@@ -1446,6 +1451,7 @@ __host__ __device__ __forceinline__ double solve_tile(X& ex, T* lds, const Patch
   const int64_t Nc = P.Nc;
   const T* u = Uin + P.ubase;
   T* uo = Uout + P.ubase;
+  T* kp = KEEP ? keep + P.ubase : nullptr;
   const LdRel<T> wa{Win + P.wbase, (uint32_t)P.Nwc};
   // time step of the next step: per direction, whether the tile's last cells sit at a domain
   // boundary (their upper face is then the exchange's copy of the last owned face)
@@ -1545,11 +1551,23 @@ __host__ __device__ __forceinline__ double solve_tile(X& ex, T* lds, const Patch
       const int lx = it % tx, ly = (it / tx) % ty, lz = it / (tx * ty);
       const int64_t cell = cell_of(P, i0 + lx, j0 + ly, k0 + lz);
       T hn[5];  // the cell's new density, momentum, energy
-      if (!SPLIT || phase == 0) {
+      const bool hyd = !SPLIT || phase == 0, mag = !SPLIT || phase == 1;
+      T u0[8];  // KEEP: the fields this phase updates, all read before any write
+      if constexpr (KEEP) {
+        if (hyd)
+          for (int m = 0; m < 5; ++m) u0[m] = u[m * Nc + cell];
+        if (mag)
+          for (int m = 5; m < 8; ++m) u0[m] = u[m * Nc + cell];
+        if (hyd)
+          for (int m = 0; m < 5; ++m) kp[m * Nc + cell] = u0[m];
+        if (mag)
+          for (int m = 5; m < 8; ++m) kp[m * Nc + cell] = u0[m];
+      }
+      if (hyd) {
         const int fxl = lx + (TX + 1) * (ly + TY * lz), fyl = lx + TX * (ly + (TY + 1) * lz),
                   fzl = lx + TX * (ly + TY * lz);
         for (int m = 0; m < 5; ++m) {
-          T v = u[m * Nc + cell];
+          T v = KEEP ? u0[m] : u[m * Nc + cell];
           if (ax) v = v - dtdx[0] * (fx[m * SH::NFX + fxl + 1] - fx[m * SH::NFX + fxl]);
           if (ay) v = v - dtdx[1] * (fy[m * SH::NFY + fyl + TX] - fy[m * SH::NFY + fyl]);
           if (az) v = v - dtdx[2] * (fz[m * SH::NFZ + fzl + TX * TY] - fz[m * SH::NFZ + fzl]);
@@ -1565,7 +1583,8 @@ __host__ __device__ __forceinline__ double solve_tile(X& ex, T* lds, const Patch
         const T* E0 = eg;
         const T* E1 = eg + Nc;
         const T* E2 = eg + 2 * Nc;
-        T bx = u[5 * Nc + cell], by = u[6 * Nc + cell], bz = u[7 * Nc + cell];
+        T bx = KEEP ? u0[5] : u[5 * Nc + cell], by = KEEP ? u0[6] : u[6 * Nc + cell],
+          bz = KEEP ? u0[7] : u[7 * Nc + cell];
         if (ay) bx = bx + dtdx[1] * (E2[cell + oy] - E2[cell]);
         if (az) bx = bx - dtdx[2] * (E1[cell + oz] - E1[cell]);
         if (az) by = by + dtdx[2] * (E0[cell + oz] - E0[cell]);
@@ -1592,7 +1611,8 @@ __host__ __device__ __forceinline__ double solve_tile(X& ex, T* lds, const Patch
         const int zl = lx + (TX + 1) * (ly + (TY + 1) * lz);
         const int xl = lx + TX * (ly + (TY + 1) * lz);
         const int yl = lx + (TX + 1) * (ly + TY * lz);
-        T bx = u[5 * Nc + cell], by = u[6 * Nc + cell], bz = u[7 * Nc + cell];
+        T bx = KEEP ? u0[5] : u[5 * Nc + cell], by = KEEP ? u0[6] : u[6 * Nc + cell],
+          bz = KEEP ? u0[7] : u[7 * Nc + cell];
         if (ay) bx = bx + dtdx[1] * (ez[zl + (TX + 1)] - ez[zl]);
         if (az) bx = bx - dtdx[2] * (ey[yl + (TX + 1) * TY] - ey[yl]);
         if (az) by = by + dtdx[2] * (exx[xl + TX * (TY + 1)] - exx[xl]);

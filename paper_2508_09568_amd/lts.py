@@ -16,11 +16,11 @@ def run_graph(bunch, U, dx, nbr, t_end, dt_fixed=None, dt_quantum=0.0, steps_per
     from .binding import MhdError
     P = bunch.P
     dev = U.device
-    Ua, Ub, Up = U.clone(), torch.empty_like(U), U.clone()
+    Ua, Up = U.clone(), U.clone()
     t = torch.zeros(P, dtype=torch.float64, device=dev)
     tp = torch.zeros(P, dtype=torch.float64, device=dev)
     dt = torch.zeros(P, dtype=torch.float64, device=dev)
-    bunch.lts_graph_capture(steps_per_graph, Ua, Ub, Up, t, tp, dt, dx, nbr, t_end,
+    bunch.lts_graph_capture(steps_per_graph, Ua, None, Up, t, tp, dt, dx, nbr, t_end,
                             dt_fixed=dt_fixed, dt_quantum=dt_quantum)
     n = 0
     while n < max_steps:
@@ -45,7 +45,7 @@ def run(bunch, U, dx, nbr, t_end, dt_fixed=None, dt_quantum=0.0, check_every=16,
     from .binding import MhdError
     P = bunch.P
     dev = U.device
-    Ua, Ub, Up = U.clone(), torch.empty_like(U), U.clone()
+    Ua, Up = U.clone(), U.clone()
     t = torch.zeros(P, dtype=torch.float64, device=dev)
     tp = torch.zeros(P, dtype=torch.float64, device=dev)
     dt = torch.zeros(P, dtype=torch.float64, device=dev)
@@ -53,7 +53,7 @@ def run(bunch, U, dx, nbr, t_end, dt_fixed=None, dt_quantum=0.0, check_every=16,
     nwork = torch.zeros((), dtype=torch.int64, device=dev)
     n = 0
     while n < max_steps:
-        bunch.lts_step(Ua, Ub, Up, t, tp, dt, dx, nbr, t_end, dt_fixed=dt_fixed,
+        bunch.lts_step(Ua, None, Up, t, tp, dt, dx, nbr, t_end, dt_fixed=dt_fixed,
                        dt_quantum=dt_quantum)
         adv = dt > 0
         count += adv

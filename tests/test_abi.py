@@ -145,8 +145,9 @@ def test_predictor_modes_are_listed_and_range_checked(B, dims, shapes):
 
 
 def test_local_time_step_validates_its_arguments_on_the_host(B):
-    """mhd_bunch_lts_step rejects missing or aliased time arrays, a negative or non-finite
-    quantum and a NaN end time before any launch, and needs a bound handle."""
+    """mhd_bunch_lts_step rejects missing state buffers or time arrays, aliased time arrays, a
+    negative or non-finite quantum and a NaN end time before any launch, and needs a bound
+    handle; U_new (not used) may be NULL."""
     rc, h = _create(B, [[16, 16, 16]] * 2)
     assert rc == B.MHD_OK
     bufs = [np.zeros(8) for _ in range(9)]
@@ -167,6 +168,7 @@ def test_local_time_step_validates_its_arguments_on_the_host(B):
             assert call(**kw) == B.MHD_EINVAL, kw         # the given steps alias written arrays
         assert call() == B.MHD_ESTATE                      # valid, but the handle is not bound
         assert call(dt_fixed=None, q=0.5) == B.MHD_ESTATE
+        assert call(U_new=None) == B.MHD_ESTATE            # U_new is not used: may be NULL
     finally:
         B.mhd_bunch_destroy(h)
 

@@ -69,10 +69,16 @@ def test_one_step_fill_and_bookkeeping_match_oracle_bitwise(precision):
     assert np.array_equal(host(dtd), dt_want)
     assert np.array_equal(host(tpd), np.where(ready, t, tp))
     assert np.array_equal(host(td), np.where(ready & (dt_want >= t_end - t), t_end, t + dt_want))
+    # previous slice: a ready patch's owned values before the update (its guard cells are not
+    # written: the guard fill reads owned values only); patches at rest untouched
     gp = host(Upd)
+    Upw = Up.astype(want.dtype)
     for p in range(L.P):
-        a, b = L.view(gp, p), L.view(want if ready[p] else Up.astype(want.dtype), p)
-        assert np.array_equal(a, b), p
+        if ready[p]:
+            assert np.array_equal(L.interior(gp, p), L.interior(want, p)), p
+        else:
+            assert np.array_equal(L.view(gp, p), L.view(Upw, p)), p
+    assert np.array_equal(gp[guard], Upw[guard])
 
 
 def test_run_with_fixed_steps_matches_oracle_driver():
