@@ -696,10 +696,36 @@ def main():
                     help="only the FP64 local-time-stepping run with each patch's own CFL step "
                          "(eager launches, for a kernel trace), in the launch configuration "
                          "--tile / --predictor / --split, then exit")
+    ap.add_argument("--bw-probe", action="store_true",
+                    help="only measure the device's memory ceilings (fill, sum and copy of "
+                         "4 GiB FP64, HIP events, 10 repetitions each) and exit")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run 5 plain device-to-device copies of this many bytes (HBM "
                          "counter calibration under rocprofv3 --pmc) and exit")
     args = ap.parse_args()
+    if args.bw_probe:
+        import torch
+        nbytes = 4 << 30
+        x = torch.full((nbytes // 8,), 1.0, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+
+        def per_call(f, reps=10):
+            f()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                f()
+            b.record()
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / reps / 1e3
+
+        tw, tr, tc = per_call(lambda: x.fill_(3.0)), per_call(lambda: x.sum()), \
+            per_call(lambda: y.copy_(x))
+        print(json.dumps({"bw_probe_bytes": nbytes, "write_tb_s": nbytes / tw / 1e12,
+                          "read_tb_s": nbytes / tr / 1e12,
+                          "copy_read_plus_write_tb_s": 2 * nbytes / tc / 1e12}), flush=True)
+        return
     if args.copy_probe:
         import torch
         a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
