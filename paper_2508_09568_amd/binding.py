@@ -11,7 +11,10 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmhdbunch.so")
+# MHD_PARITY_BUILD=1 loads the parity build of the same sources (no contraction, correctly
+# rounded division and square root), which the parity tests use for their tightest bars
+PARITY_BUILD = os.environ.get("MHD_PARITY_BUILD") == "1"
+LIB_PATH = os.path.join(HERE, "libmhdbunch_strict.so" if PARITY_BUILD else "libmhdbunch.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "mhd_bunch.h")
 
 if not os.path.exists(LIB_PATH):

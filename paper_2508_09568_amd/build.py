@@ -1,4 +1,8 @@
-"""Compile the HIP library libmhdbunch.so for gfx950 (in-tree, next to this file).
+"""Compile the HIP library libmhdbunch.so for gfx950 (in-tree, next to this file), and from the
+same sources its parity build libmhdbunch_strict.so (no multiply-add contraction, correctly
+rounded division and square root: every operation rounded as a plain CPU evaluation of the
+same expressions rounds it), which the parity tests use for the comparisons whose bar is
+below what contraction changes.
 
 The device code is compiled by hipcc; the shared library is linked against the HIP
 runtime that PyTorch loads (its bundled libamdhip64.so), so a process that uses torch
@@ -14,8 +18,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "mhd_bunch.hip")
-OBJ = os.path.join(HERE, "csrc", "mhd_bunch.o")
 LIB = os.path.join(HERE, "libmhdbunch.so")
+LIB_STRICT = os.path.join(HERE, "libmhdbunch_strict.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -28,6 +32,8 @@ FLAGS = [
     "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
 ]
+STRICT_FLAGS = [f for f in FLAGS if f != "-ffp-contract=on"] + ["-ffp-contract=off",
+                                                                 "-DMHD_STRICT_IEEE"]
 
 
 def torch_lib_dir() -> str:
@@ -36,20 +42,28 @@ def torch_lib_dir() -> str:
 
 
 def build(verbose: bool = False) -> str:
+    """Both libraries, compiled in parallel; returns the path of the product library."""
     tl = torch_lib_dir()
     if not os.path.exists(os.path.join(tl, "libamdhip64.so")):
         raise RuntimeError(f"no libamdhip64.so in {tl}: a ROCm build of torch is required")
-    cmds = [
-        [HIPCC, *FLAGS, "-c", SRC, "-o", OBJ],
-        ["g++", "-shared", "-o", LIB + ".tmp", OBJ, f"-L{tl}", "-l:libamdhip64.so",
-         f"-Wl,-rpath,{tl}", "-Wl,--no-undefined", "-Wl,--no-as-needed"],
-    ]
-    for cmd in cmds:
+    jobs = [(LIB, FLAGS), (LIB_STRICT, STRICT_FLAGS)]
+    procs = []
+    for lib, flags in jobs:
+        cmd = [HIPCC, *flags, "-c", SRC, "-o", lib + ".o"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
+    bad = [cmd for cmd, p in procs if p.wait() != 0]
+    if bad:
+        raise subprocess.CalledProcessError(1, bad[0])
+    for lib, _ in jobs:
+        cmd = ["g++", "-shared", "-o", lib + ".tmp", lib + ".o", f"-L{tl}", "-l:libamdhip64.so",
+               f"-Wl,-rpath,{tl}", "-Wl,--no-undefined", "-Wl,--no-as-needed"]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    os.remove(OBJ)
+        os.replace(lib + ".tmp", lib)
+        os.remove(lib + ".o")
     return LIB
 
 

@@ -26,16 +26,24 @@ __host__ __device__ __forceinline__ double m_max(double a, double b) { return fm
 //          iterations of r <- r + r (1 - x r); square root: the coupled iteration for
 //          g ~ sqrt(x), h ~ 1 / (2 sqrt(x)) with one residual correction), within about
 //          1 ulp of the exact result.
-// The host versions (CPU builds of this header) are the plain operations.
+// The host versions (CPU builds of this header) are the plain operations, and so are the
+// device versions of a build with MHD_STRICT_IEEE defined (correctly rounded division and
+// square root): with contraction off as well, that build rounds every operation as a plain
+// CPU evaluation of the same expressions does.
+#if defined(__HIP_DEVICE_COMPILE__) && !defined(MHD_STRICT_IEEE)
+#define MHD_HW_MATH 1
+#else
+#define MHD_HW_MATH 0
+#endif
 __host__ __device__ __forceinline__ float m_rcp(float x) {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if MHD_HW_MATH
   return __builtin_amdgcn_rcpf(x);
 #else
   return 1.0f / x;
 #endif
 }
 __host__ __device__ __forceinline__ double m_rcp(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if MHD_HW_MATH
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
   r = fma(r, e, r);
@@ -46,14 +54,14 @@ __host__ __device__ __forceinline__ double m_rcp(double x) {
 #endif
 }
 __host__ __device__ __forceinline__ float m_sqrt(float x) {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if MHD_HW_MATH
   return __builtin_amdgcn_sqrtf(x);
 #else
   return sqrtf(x);
 #endif
 }
 __host__ __device__ __forceinline__ double m_sqrt(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if MHD_HW_MATH
   const double y = __builtin_amdgcn_rsq(x);
   double g = x * y, h = 0.5 * y;
   const double r = fma(-g, h, 0.5);
@@ -69,7 +77,7 @@ __host__ __device__ __forceinline__ double m_sqrt(double x) {
 // square root of a strictly positive finite argument (no zero guard)
 __host__ __device__ __forceinline__ float m_sqrt_pos(float x) { return m_sqrt(x); }
 __host__ __device__ __forceinline__ double m_sqrt_pos(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if MHD_HW_MATH
   const double y = __builtin_amdgcn_rsq(x);
   double g = x * y, h = 0.5 * y;
   const double r = fma(-g, h, 0.5);
@@ -82,14 +90,14 @@ __host__ __device__ __forceinline__ double m_sqrt_pos(double x) {
 #endif
 }
 __host__ __device__ __forceinline__ float m_rsqrt(float x) {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if MHD_HW_MATH
   return __builtin_amdgcn_rsqf(x);
 #else
   return 1.0f / sqrtf(x);
 #endif
 }
 __host__ __device__ __forceinline__ double m_rsqrt(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if MHD_HW_MATH
   double y = __builtin_amdgcn_rsq(x);
   double e = fma(-x * y, y, 1.0);
   y = fma(0.5 * y, e, y);

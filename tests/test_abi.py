@@ -25,6 +25,18 @@ def test_library_exports_every_declared_symbol(B):
         assert hasattr(B._lib, n), n
 
 
+def test_parity_build_exports_every_declared_symbol(B):
+    """The parity build (same sources, no contraction, IEEE division and square root) is
+    built beside the library and exports the same functions."""
+    import os
+    path = os.path.join(os.path.dirname(B.LIB_PATH), "libmhdbunch_strict.so")
+    assert os.path.exists(path), path
+    lib = C.CDLL(path)
+    for n in B.header_functions():
+        assert hasattr(lib, n), n
+    assert len(B._hip_runtimes()) == 1
+
+
 def _desc(B, dims, **kw):
     dims = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
     base = dict(guard=3, precision=8, gamma=5 / 3, cfl=0.4, limiter=0, rho_floor=1e-12,

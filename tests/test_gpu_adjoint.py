@@ -58,15 +58,16 @@ def _case(name):
 # x): the HLLD star-state denominator D is ~1e-4 of its O(1) terms and derivatives carry
 # 1/D^2, so FMA-contracted GPU arithmetic and the oracle's plain rounding differ by ~4e-10
 # per step there (a CPU build of the same device code reproduces 1.4e-12 without and 4.3e-10
-# with FMA contraction).  Elsewhere the identity holds to round-off.
+# with FMA contraction; the parity build, test_gpu_parity_build, measures 1.4e-12).
+# Elsewhere the identity holds to round-off.
 DOT_TOL = {"adjoint16": 1e-8}
 
 
-@pytest.mark.parametrize("name", ["adjoint16", "ot32", "sod", "wave2d_yz", "ragged_frozen"])
-def test_adjoint_dot_product_against_oracle_jvp(name):
-    """<J v, w> (oracle dual numbers) = <v, J^T w> (GPU adjoint) for one update."""
+def dot_product_error(name):
+    """Relative difference of <J v, w> (oracle dual numbers) and <v, J^T w> (GPU adjoint) for
+    one update of case `name`, and whether the adjoint of every guard entry is zero (guards
+    are copies of owned entries, whose adjoints they were folded onto)."""
     import oracle
-    log(f"[gpu] adjoint dot-product case={name}")
     L, U, dx, nbr, gam = _case(name)
     U = np.ascontiguousarray(U, dtype=np.float64).copy()
     if nbr is not None:
@@ -94,9 +95,16 @@ def test_adjoint_dot_product_against_oracle_jvp(name):
     a = float(np.dot(Jv[M], w[M]))
     b = float(np.dot(v[inp], JTw[inp]))
     log(f"    <Jv,w>={a:.16e} <v,J^T w>={b:.16e} rel={abs(a - b) / abs(a):.2e}")
-    assert abs(a - b) <= DOT_TOL.get(name, 1e-12) * abs(a)
-    if nbr is not None:
-        assert np.all(JTw[~M] == 0.0)
+    return abs(a - b) / abs(a), bool(nbr is None or np.all(JTw[~M] == 0.0))
+
+
+@pytest.mark.parametrize("name", ["adjoint16", "ot32", "sod", "wave2d_yz", "ragged_frozen"])
+def test_adjoint_dot_product_against_oracle_jvp(name):
+    """<J v, w> (oracle dual numbers) = <v, J^T w> (GPU adjoint) for one update."""
+    log(f"[gpu] adjoint dot-product case={name}")
+    rel, guards_zero = dot_product_error(name)
+    assert rel <= DOT_TOL.get(name, 1e-12)
+    assert guards_zero
 
 
 def _fd_fixture():
@@ -189,16 +197,17 @@ def test_checkpointing_and_determinism():
     assert np.array_equal(grads[2], grads[3])
 
 
-def test_adjoint_case_gradient_against_oracle_and_finite_differences():
+def adjoint_case_errors():
     """64^3 periodic (8 patches of 32^3), fast wave + noise, 20 steps at fixed dt,
     checkpoint every 5: gradient of L = 1/2 sum (rho^20 - rho_target)^2 w.r.t. the initial
-    state.  (a) along a random direction against the oracle's dual-number derivative of
-    the whole rollout; (b) at the 50 seeded entries against central differences of the
-    oracle's rollout in extended precision and against its dual-number derivative."""
+    state.  Returns (a) the relative error along a random direction against the oracle's
+    dual-number derivative of the whole rollout, (b) at the 50 seeded entries the relative
+    errors against central differences of the oracle's rollout in extended precision and
+    against its dual-number derivative, and whether the guards' gradient is zero and every
+    fixture entry was on one branch."""
     import torch
 
     import oracle
-    log("[gpu] adjoint configuration: 20 steps, checkpoint 5, 64^3")
     w = W.adjoint_case()
     L = w.layout
     prm = oracle.Params(gamma=w.gamma)
@@ -228,7 +237,7 @@ def test_adjoint_case_gradient_against_oracle_and_finite_differences():
     L0 = loss(x)
     L0.backward()
     grad = host(x.grad)
-    assert np.all(grad[~M] == 0.0)
+    guards_zero = bool(np.all(grad[~M] == 0.0))
     # (a) directional derivative of the oracle's 20-step rollout
     rng = np.random.default_rng(7)
     v = rng.standard_normal(L.total) * M
@@ -238,8 +247,6 @@ def test_adjoint_case_gradient_against_oracle_and_finite_differences():
     dL_gpu = float(np.dot(grad[M], v[M]))
     rel = abs(dL_gpu - dL_oracle) / abs(dL_oracle)
     log(f"    directional: oracle {dL_oracle:.15e} gpu {dL_gpu:.15e} rel {rel:.2e}")
-    # 20 steps at the degenerate point compound the per-step 4e-10 (see DOT_TOL)
-    assert rel <= 1e-6
     # (b) the 50 seeded entries of tests/golden/adjoint_case_fd50.txt: central differences
     # of the oracle's rollout in extended precision (both ends on the branch of x) and the
     # oracle's dual-number derivative, both written by tests/golden/make_adjoint_fd.py
@@ -258,6 +265,18 @@ def test_adjoint_case_gradient_against_oracle_and_finite_differences():
             f"jvp {jj:.12e} rel(fd) {ef:.2e}")
     log(f"    50 entries: max rel err vs FD {e_fd.max():.2e} (median {np.median(e_fd):.2e}), "
         f"vs oracle dual numbers {e_jv.max():.2e}")
-    assert clean.all()
-    assert e_fd.max() <= 1e-6
-    assert e_jv.max() <= 1e-6
+    return {"directional": rel, "fd": float(e_fd.max()), "duals": float(e_jv.max()),
+            "guards_zero": guards_zero, "clean": bool(clean.all())}
+
+
+def test_adjoint_case_gradient_against_oracle_and_finite_differences():
+    """The adjoint configuration's gradient (adjoint_case_errors) within 1e-6 of the oracle's
+    dual numbers and extended-precision differences: the 20-step rollout at the degenerate
+    point amplifies any rounding difference, so the parity build (no contraction) differs
+    from the oracle by the same ~3e-8 (test_gpu_parity_build)."""
+    log("[gpu] adjoint configuration: 20 steps, checkpoint 5, 64^3")
+    e = adjoint_case_errors()
+    assert e["guards_zero"] and e["clean"]
+    assert e["directional"] <= 1e-6
+    assert e["fd"] <= 1e-6
+    assert e["duals"] <= 1e-6

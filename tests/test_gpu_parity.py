@@ -66,10 +66,10 @@ STEP_CASES = ["sod", "sod8", "ot64", "wave2d_yz", "wave2d_zx", "wave1d_z", "turb
               "adjoint32"]
 
 
-@pytest.mark.parametrize("name", STEP_CASES)
-def test_step_parity_fp64(name):
+def step_errors(name):
+    """One FP64 update of case `name` against the oracle's: per-field errors in the metric of
+    reading R12 and in the plain per-field relative max-norm."""
     import oracle
-    log(f"[gpu] step parity fp64 case={name}")
     L, U, dx, nbr, gam = _case(name)
     prm = oracle.Params(gamma=gam)
     dt = oracle.cfl_many(U, L.dims, L.g, dx, prm)
@@ -85,6 +85,13 @@ def test_step_parity_fp64(name):
     plain = plain_rel_err_fields(L, got, ref)
     log(f"    per-field rel err {err}")
     log(f"    plain per-field relative max-norm (no natural-scale floor) {plain}")
+    return err, plain
+
+
+@pytest.mark.parametrize("name", STEP_CASES)
+def test_step_parity_fp64(name):
+    log(f"[gpu] step parity fp64 case={name}")
+    err, _ = step_errors(name)
     assert np.all(err <= FP64_STEP_TOL), err
 
 
