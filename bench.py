@@ -42,7 +42,7 @@ def log(*a):
 # (the hash moves on only with a source change that leaves the machine code of every measured
 # kernel as it was).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "0e5305312fd8f09741d0c326f06955281d5593124cd4a8378c49cb1fa16ce58b",
+    "sources_sha256": "dd3e6f25b04353c0f3d3e494da4ee032fe6b72c204e0b84ac63f721ea723af3d",
     "bytes_per_update": {
         "[32, 4, 2, 1]/1/3": 234.06e9,
         "[32, 8, 2, 1]/1/3": 229.05e9,
