@@ -4,6 +4,10 @@
   (solver form 2): every edge of ragged 3D patches written once by each, with the same bits,
   for both EMF solvers and both precisions (indexing, ownership, the carried corner values;
   the device build is compared the same way by the GPU tests).
+- The solver tile of a local time step (in place, previous slice written) against the
+  ordinary out-of-place tile: the same bits on every owned value, the previous slice equal to
+  the input's owned values, guards untouched (solver forms 0, 1, 2; both EMF solvers and
+  precisions).
 - The adjoint's skipped items: every forward item the adjoint gathers skip for a seed has an
   exactly zero derivative with respect to it (faces and edges against predictor slots; the
   predictor, time-n EMFs and primitives against seeds in primitives, EMFs and state)."""
@@ -37,6 +41,10 @@ def _run(tmp_path, name):
 
 def test_edge_lines_match_owned_edge_pass_bitwise(tmp_path):
     _run(tmp_path, "edge_lines")
+
+
+def test_in_place_local_step_tile_matches_out_of_place_bitwise(tmp_path):
+    _run(tmp_path, "solve_keep")
 
 
 def test_adjoint_skips_only_zero_derivatives(tmp_path):
