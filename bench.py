@@ -696,6 +696,9 @@ def main():
                     help="only the FP64 local-time-stepping run with each patch's own CFL step "
                          "(eager launches, for a kernel trace), in the launch configuration "
                          "--tile / --predictor / --split, then exit")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the adjoint workload's forward and forward + backward timing "
+                         "(for a kernel trace), then exit")
     ap.add_argument("--bw-probe", action="store_true",
                     help="only measure the device's memory ceilings (fill, sum and copy of "
                          "4 GiB FP64, HIP events, 10 repetitions each) and exit")
@@ -703,6 +706,9 @@ def main():
                     help="only run 5 plain device-to-device copies of this many bytes (HBM "
                          "counter calibration under rocprofv3 --pmc) and exit")
     args = ap.parse_args()
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_only": run_adjoint(3)}), flush=True)
+        return
     if args.bw_probe:
         import torch
         nbytes = 4 << 30
