@@ -42,7 +42,7 @@ def log(*a):
 # (the hash moves on only with a source change that leaves the machine code of every measured
 # kernel as it was).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "dd3e6f25b04353c0f3d3e494da4ee032fe6b72c204e0b84ac63f721ea723af3d",
+    "sources_sha256": "9135b0f9087483f992ccf28c99b7cd38f484677efef61fb8eba63f12cbe72e13",
     "bytes_per_update": {
         "[32, 4, 2, 1]/1/3": 234.06e9,
         "[32, 8, 2, 1]/1/3": 229.05e9,
@@ -83,7 +83,7 @@ def algorithmic_bytes_per_cell(n, g, s):
 
 
 def run_precision(w, precision, steps, warmup, flops_per_cell, tile=None, predictor=None,
-                  split=None):
+                  split=None, emf_solver=0):
     import numpy as np
     import torch
 
@@ -93,7 +93,7 @@ def run_precision(w, precision, steps, warmup, flops_per_cell, tile=None, predic
     dtype = torch.float64 if precision == 8 else torch.float32
     Ua = w.U.to(dtype=dtype, copy=True)
     Ub = torch.empty_like(Ua)
-    B = Bunch(L.dims, g=L.g, precision=precision, gamma=w.gamma, cfl=w.cfl)
+    B = Bunch(L.dims, g=L.g, precision=precision, gamma=w.gamma, cfl=w.cfl, emf_solver=emf_solver)
     nbr = torch.as_tensor(w.nbr.astype(np.int32)).cuda()
     dx = torch.as_tensor(w.dx).cuda()
     dt = torch.zeros(L.P, dtype=torch.float64, device="cuda")
@@ -688,6 +688,11 @@ def main():
                     help="skip the host-resident streamed update")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint workload's forward / backward timing")
+    ap.add_argument("--no-uct-hlld", action="store_true",
+                    help="skip the FP64 step with the UCT-HLLD edge EMF (emf_solver 1)")
+    ap.add_argument("--uct-hlld-only", action="store_true",
+                    help="only the FP64 step with the UCT-HLLD edge EMF (for a kernel trace; "
+                         "--tile / --predictor / --split as for the main step), then exit")
     ap.add_argument("--no-lts", action="store_true",
                     help="skip the local-time-stepping run")
     ap.add_argument("--lts-span", type=float, default=8.0,
@@ -764,6 +769,23 @@ def main():
     ops = oracle.ops_per_cell(p0, w.layout.dims[0], w.layout.g, 1e-4, w.dx[0],
                               oracle.Params(gamma=w.gamma))
     flops = float(ops[:4].sum())
+    ops1 = oracle.ops_per_cell(p0, w.layout.dims[0], w.layout.g, 1e-4, w.dx[0],
+                               oracle.Params(gamma=w.gamma, emf_solver=1))
+    flops_uct_hlld = float(ops1[:4].sum())
+
+    def uct_hlld_summary(r):
+        return {"emf_solver": 1, "value": r["value"], "ms_per_step": r["ms_per_step"],
+                "update_ms_per_launch": r["update_ms_per_launch"],
+                "flops_per_cell": flops_uct_hlld,
+                "alu_frac": r["update_tflops"] / PEAK_VALU_TFLOPS[8],
+                "kernels_ms": {k: v["avg_ms"] for k, v in r["kernels"].items()},
+                "tile": r["tile"]}
+
+    if args.uct_hlld_only:
+        rh = run_precision(w, 8, args.steps, args.warmup, flops_uct_hlld, args.tile,
+                           args.predictor, args.split, emf_solver=1)
+        print(json.dumps({"uct_hlld_only": uct_hlld_summary(rh)}), flush=True)
+        return
 
     if args.lts_only:
         from paper_2508_09568_amd.binding import Bunch
@@ -804,6 +826,19 @@ def main():
                             args.split)
         r32.pop("bunch")
         log(f"[bench] FP32 {r32['value']:.4e} cell-updates/s, {r32['ms_per_step']:.2f} ms/step")
+
+    uct_hlld = None
+    if not args.no_uct_hlld:
+        torch.cuda.empty_cache()
+        log(f"[bench] FP64 with the UCT-HLLD edge EMF: warmup {args.warmup}, timed {args.steps} "
+            f"steps")
+        rh = run_precision(w, 8, args.steps, args.warmup, flops_uct_hlld, args.tile,
+                           args.predictor, args.split, emf_solver=1)
+        rh.pop("bunch")
+        uct_hlld = uct_hlld_summary(rh)
+        uct_hlld["time_vs_uct_hll"] = rh["ms_per_step"] / r64["ms_per_step"]
+        log(f"[bench] UCT-HLLD {rh['value']:.4e} cell-updates/s, {rh['ms_per_step']:.2f} ms/step "
+            f"({uct_hlld['time_vs_uct_hll']:.2f}x the UCT-HLL step)")
 
     batched = None
     if not args.no_batched:
@@ -900,6 +935,7 @@ def main():
             "kernels_ms": {k: v["avg_ms"] for k, v in r32["kernels"].items()},
             "tile": r32["tile"],
         },
+        "uct_hlld": uct_hlld,
         "batched": batched,
         "local_time_stepping": lts_res,
         "adjoint": adj,

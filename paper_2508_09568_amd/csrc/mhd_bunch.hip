@@ -255,9 +255,14 @@ void k_edges(
 
 // the same half-step edge EMFs as edge lines (solver form 3, patches with all three
 // directions active): BLK consecutive lines of one patch per work-group, each line marched by
-// one thread; registers alone set the occupancy, three waves per SIMD (<= 168 VGPRs)
+// one thread; registers alone set the occupancy: three waves per SIMD (<= 168 VGPRs), two
+// for the FP64 UCT-HLLD lines, which hold four corner states and spill within 168
 template <typename T, int EMF>
-__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(3))) void k_edge_lines(
+struct EdgeLineWaves {
+  static constexpr int value = EMF == 1 && sizeof(T) == 8 ? 2 : 3;
+};
+template <typename T, int EMF>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(EdgeLineWaves<T, EMF>::value))) void k_edge_lines(
     const PatchDev* __restrict__ pt, const BoxBlock* __restrict__ blk, T* __restrict__ S,
     const double* __restrict__ dt, Consts<T> c, int g, int nb0, int remap,
     const int* __restrict__ dcount) {
