@@ -25,6 +25,16 @@ def test_library_exports_every_declared_symbol(B):
         assert hasattr(B._lib, n), n
 
 
+def test_parity_build_differs_only_in_rounding_flags():
+    """The parity build compiles the same sources with the same flags except that multiply-add
+    contraction is off and MHD_STRICT_IEEE selects the correctly rounded division and square
+    root."""
+    from paper_2508_09568_amd import build as hb
+    assert "-ffp-contract=on" in hb.FLAGS and "-ffp-contract=on" not in hb.STRICT_FLAGS
+    rest = [f for f in hb.FLAGS if f != "-ffp-contract=on"]
+    assert hb.STRICT_FLAGS == rest + ["-ffp-contract=off", "-DMHD_STRICT_IEEE"]
+
+
 def test_parity_build_exports_every_declared_symbol(B):
     """The parity build (same sources, no contraction, IEEE division and square root) is
     built beside the library and exports the same functions."""
