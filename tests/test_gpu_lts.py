@@ -261,6 +261,35 @@ def test_3d_run_with_own_cfl_steps_matches_oracle_driver(case):
     assert err.max() <= 1e-12 * cnt.max(), err
 
 
+def test_in_place_local_steps_agree_bitwise_across_solver_forms():
+    """The update of a local step runs in place and its solver tiles write the previous slice
+    (k_solve_keep): one-phase, two-phase and faces-after-edge-pass tiles and the edge-line pass
+    give the same bits over a whole own-CFL run (3D periodic turbulence), as the out-of-place
+    update does."""
+    import torch
+
+    import oracle
+    from paper_2508_09568_amd import lts
+    log("[gpu] lts in place: solver forms 0-3 over one run")
+    w, U = _turb3d("periodic")
+    L = w.layout
+    prm = oracle.Params(gamma=w.gamma, cfl=w.cfl)
+    t_end = 3.0 * float(oracle.cfl_many(U, L.dims, L.g, w.dx, prm).min())
+    Ud, dxd, nbd = dev(U), dev(w.dx), dev(w.nbr.astype(np.int32))
+    runs = []
+    for form in range(4):
+        B = make_bunch(L, w.gamma, cfl=w.cfl)
+        B.set_solver_split(form)
+        Ug, tg, n, cg = lts.run(B, Ud, dxd, nbd, t_end, check_every=1)
+        assert B.check() == 0
+        runs.append((Ug, tg, cg, n))
+    log(f"    {runs[0][3]} steps, updates per patch {int(runs[0][2].min())}..{int(runs[0][2].max())}")
+    for Ug, tg, cg, n in runs[1:]:
+        assert n == runs[0][3]
+        assert torch.equal(tg, runs[0][1]) and torch.equal(cg, runs[0][2])
+        assert torch.equal(Ug, runs[0][0])
+
+
 def test_3d_fp32_run_against_fp64_oracle():
     import oracle
     import torch
