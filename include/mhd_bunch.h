@@ -79,10 +79,9 @@ typedef struct {
 /* Validates the description and builds the host-side patch and launch tables.  No
  * device memory is touched.  *out receives a handle to free with mhd_bunch_destroy.
  * MHD_EUNSUPPORTED for patches of different dimensionality, and for a patch whose scratch
- * of one update (11 (n+2g)^D + 38 (n+2)^D values, D active directions; in double the
- * predictor rows along x are padded to a multiple of 4 cells) exceeds 4 GiB: the kernels
- * address it by 32-bit offsets (g = 3: up to 218^3 cells in double and 276^3 in float in 3D,
- * 3306^2 in double in 2D). */
+ * of one update (11 (n+2g)^D + 38 (n+2)^D values, D active directions) exceeds 4 GiB: the
+ * kernels address it by 32-bit offsets (g = 3: up to 219^3 cells in double and 276^3 in
+ * float in 3D, 3307^2 in double in 2D). */
 mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* desc);
 void mhd_bunch_destroy(mhd_bunch* h);
 

@@ -1435,15 +1435,10 @@ mhd_status mhd_bunch_create(mhd_bunch** out, const mhd_bunch_desc* d) {
       P.off[dd] = (act >> dd & 1) ? st[dd] : 0;
       Nw[dd] = (act >> dd & 1) ? P.n[dd] + 2 : 1;
     }
-    // FP64 rows of the predictor box padded to whole 32-byte sectors (a 32-cell patch: 36 cells
-    // of which 34 are used): the predictor tiles' row pieces then start on sector boundaries
-    // (measured: predictor -8 %, edge lines -4 %, faces tile +3 %; FP32 rows stay dense, its
-    // whole-row predictor tiles lost 25 % with padding)
-    const int rw = (act & 1) && h->prec == 8 ? (Nw[0] + 3) / 4 * 4 : Nw[0];
     P.woff[0] = (act & 1) ? 1 : 0;
-    P.woff[1] = (act & 2) ? rw : 0;
-    P.woff[2] = (act & 4) ? (int64_t)rw * Nw[1] : 0;
-    P.Nwc = (int64_t)rw * Nw[1] * Nw[2];
+    P.woff[1] = (act & 2) ? Nw[0] : 0;
+    P.woff[2] = (act & 4) ? (int64_t)Nw[0] * Nw[1] : 0;
+    P.Nwc = (int64_t)Nw[0] * Nw[1] * Nw[2];
     // the kernels address a patch's scratch block by 32-bit byte offsets from its base
     if ((11 * P.Nc + NW * P.Nwc) * (int64_t)h->prec > (int64_t)UINT32_MAX) {
       delete h;

@@ -87,12 +87,11 @@ def test_mixed_dimensionality_is_unsupported(B):
     assert rc == B.MHD_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("prec,n,ok", [(8, 218, True), (8, 219, False), (4, 276, True),
+@pytest.mark.parametrize("prec,n,ok", [(8, 219, True), (8, 220, False), (4, 276, True),
                                          (4, 277, False)])
 def test_patch_scratch_beyond_32bit_offsets_is_unsupported(B, prec, n, ok):
     """The kernels address one patch's scratch block by 32-bit byte offsets: the largest
-    3D patch with guard 3 is 218^3 cells in double (predictor rows padded to 32 bytes),
-    276^3 in float."""
+    3D patch with guard 3 is 219^3 cells in double, 276^3 in float."""
     rc, h = _create(B, [[n, n, n]], precision=prec)
     assert rc == (B.MHD_OK if ok else B.MHD_EUNSUPPORTED)
     if ok:

@@ -450,7 +450,7 @@ def test_uneven_full_size_sampled_fp64():
     _sampled_parity(w, 8, samples, dt_local=True, tol=FP64_STEP_TOL)
 
 
-@pytest.mark.parametrize("precision,n,tune", [(8, 218, False), (8, 218, True), (4, 276, True)])
+@pytest.mark.parametrize("precision,n,tune", [(8, 219, False), (8, 219, True), (4, 276, True)])
 def test_largest_patch_matches_oracle(precision, n, tune):
     """One periodic patch at the largest size the library accepts, its scratch block just
     under 4 GiB (the kernels address it by 32-bit byte offsets): guard fill, time step and
